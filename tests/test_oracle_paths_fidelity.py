@@ -1,0 +1,89 @@
+"""Pins of the path-score brute force and the fidelity closed form."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fidelity, paths
+from circuits import diagonal53, grid, random_circuit
+
+
+def test_chain_by_hand():
+    # 3-site chain 0 -(a=2)- 1 -(b=3)- 2.
+    # order 0,1,2: Cost({0},1) = a*b = 6, then Cost({0,1},2) = b = 3 -> 9
+    # order 1,0,2: Cost({1},0) = a*b = 6, Cost({0,1},2) = 3 -> 9
+    # order 0,2,1: Cost({0},2) = a*b = 6 (no shared leg), Cost({0,2},1) = 6 -> 12
+    # order 2,1,0: Cost({2},1) = a*b = 6, Cost({1,2},0) = a = 2 -> 8 (optimal)
+    edges, dims = [(0, 1), (1, 2)], [2, 3]
+    assert paths.score([0, 1, 2], 3, edges, dims)[0] == 9
+    assert paths.score([0, 2, 1], 3, edges, dims)[0] == 12
+    assert paths.score([2, 1, 0], 3, edges, dims)[0] == 8
+    assert paths.brute_force(3, edges, dims)[0] == 8  # also reached by 1,2,0
+
+
+def test_triangle_by_hand():
+    # triangle with dims 2 (0-1), 4 (1-2), 8 (0-2): every order costs
+    # Cost(first pair) = product of all three dims = 64, then the remaining two
+    # open legs meet the last site: their product.
+    edges, dims = [(0, 1), (1, 2), (0, 2)], [2, 4, 8]
+    s, _ = paths.score([0, 1, 2], 3, edges, dims)
+    assert s == 64 + 4 * 8
+    assert paths.brute_force(3, edges, dims)[0] == 64 + 2 * 4
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_equals_subset_dp(seed):
+    rng = np.random.default_rng(seed)
+    n = 7
+    edges = set()
+    for q in range(1, n):  # spanning tree + extra edges
+        edges.add((int(rng.integers(q)), q))
+    while len(edges) < n + 3:
+        a, b = sorted(rng.choice(n, 2, replace=False))
+        edges.add((int(a), int(b)))
+    edges = sorted(edges)
+    dims = [int(2 ** rng.integers(1, 4)) for _ in edges]
+    assert paths.brute_force(n, edges, dims)[0] == paths.subset_dp(n, edges, dims)
+
+
+def test_intermediate_size_tracks_open_legs():
+    g = grid(2, 3)
+    dims = [2] * len(g.edges)
+    _, big = paths.score([0, 1, 2, 3, 4, 5], g.n, g.edges, dims)
+    # after {0,1,2} the open legs are the three verticals: 2^3
+    assert big == 8
+
+
+def test_fidelity_closed_form_53q():
+    # 53-qubit diagonal lattice, 12 cycles ABCDCDAB, no final layer:
+    # 636 single-qubit gates, 258 fSim gates.
+    c = random_circuit(diagonal53(), 12, 3, final_layer=False)
+    n1, n2 = c.count()
+    assert (n1, n2) == (636, 258)
+    f = fidelity.fidelity(n1, n2, 53)
+    assert abs(f - 9.314e-3) < 5e-6
+    assert abs(fidelity.n_samples(f) / 1.0375e5 - 1) < 2e-3
+
+
+def test_fidelity_closed_form_with_final_layer():
+    c = random_circuit(diagonal53(), 12, 3)
+    n1, n2 = c.count()
+    assert (n1, n2) == (689, 258)
+    f = fidelity.fidelity(n1, n2, 53)
+    assert abs(f - 8.556e-3) < 5e-6
+
+
+def test_fidelity_small_grid():
+    c = random_circuit(grid(3, 4), 8, 1, final_layer=False)
+    n1, n2 = c.count()
+    assert (n1, n2) == (96, 34)
+    assert abs(fidelity.fidelity(n1, n2, 12) - 0.436) < 5e-4
+
+
+def test_fidelity_limits():
+    assert fidelity.fidelity(0, 0, 0) == 1.0
+    assert fidelity.n_samples(1.0) == 9.0
+    # one two-qubit gate only
+    assert fidelity.fidelity(0, 1, 0) == pytest.approx(1 - 0.0062)
+    assert fidelity.fidelity(0, 0, 1) == pytest.approx(1 - 0.038)
