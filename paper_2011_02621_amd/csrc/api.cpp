@@ -1,0 +1,531 @@
+// extern "C" boundary: argument checks, error capture, contexts, plans and
+// the serving loop.  No C++ exception crosses into the caller.
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <list>
+#include <new>
+#include <thread>
+
+#include "internal.h"
+
+namespace tns {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(tns_status code, const std::string &msg) { throw Error(code, msg); }
+
+template <typename F>
+static tns_status guard(F &&f) {
+    try {
+        f();
+        return TNS_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return TNS_E_OUT_OF_MEMORY;
+    } catch (const std::exception &e) {
+        set_last_error(std::string("internal error: ") + e.what());
+        return TNS_E_DEVICE;
+    } catch (...) {
+        set_last_error("unknown internal error");
+        return TNS_E_DEVICE;
+    }
+}
+
+static void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(TNS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------------------------
+// serving: requests are cut into chunks of bitstrings; worker threads (one
+// HIP stream and workspace each) take chunks round-robin over the active
+// requests, so a request arriving while others run is admitted as soon as a
+// worker frees up and its chunks overlap with theirs on the device.
+
+using clk = std::chrono::steady_clock;
+
+struct Request {
+    const Plan *plan = nullptr;
+    int64_t n = 0;
+    const uint8_t *bits = nullptr;
+    double *amps = nullptr;
+    int64_t chunk = 1;
+    int64_t next = 0;            // next bitstring to hand out
+    int64_t finished = 0;        // bitstrings completed
+    int running = 0;             // chunks in flight
+    volatile int cancel = 0;
+    tns_status status = TNS_OK;
+    bool done = false;
+    std::string error;
+    clk::time_point t_submit, t_start, t_end;
+    bool started = false;
+    std::mutex m;
+    std::condition_variable cv;
+};
+
+struct Server {
+    Ctx *ctx = nullptr;
+    std::vector<std::thread> workers;
+    std::vector<void *> streams;
+    std::vector<Workspace> ws;
+    std::mutex m;
+    std::condition_variable cv;
+    std::list<Request *> active;
+    std::list<Request *>::iterator rr;
+    bool stop = false;
+    uint64_t worker_budget = 0;
+
+    void start(Ctx *c, int n_workers) {
+        ctx = c;
+        worker_budget = ctx->budget / (uint64_t)(n_workers + 1);
+        streams.resize(n_workers);
+        ws.resize(n_workers);
+        for (int i = 0; i < n_workers; ++i) {
+            hipStream_t s;
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            hip_check(hipStreamCreate(&s), "hipStreamCreate");
+            streams[i] = s;
+        }
+        rr = active.end();
+        for (int i = 0; i < n_workers; ++i) workers.emplace_back([this, i] { loop(i); });
+    }
+
+    void shutdown() {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto &t : workers) t.join();
+        for (size_t i = 0; i < streams.size(); ++i) {
+            ws[i].release(ctx, streams[i]);
+            (void)hipStreamDestroy((hipStream_t)streams[i]);
+        }
+    }
+
+    void finish(Request *r, tns_status st, const std::string &err) {
+        std::lock_guard<std::mutex> lk(r->m);
+        if (st != TNS_OK && r->status == TNS_OK) {
+            r->status = st;
+            r->error = err;
+        }
+    }
+
+    // called with m held
+    Request *pick(int64_t &b0, int64_t &b1) {
+        if (active.empty()) return nullptr;
+        auto it = rr == active.end() ? active.begin() : rr;
+        for (size_t tries = 0; tries < active.size(); ++tries) {
+            Request *r = *it;
+            ++it;
+            if (it == active.end()) it = active.begin();
+            if (r->next < r->n && r->status == TNS_OK && !r->cancel) {
+                b0 = r->next;
+                b1 = std::min(r->n, b0 + r->chunk);
+                r->next = b1;
+                r->running++;
+                if (!r->started) {
+                    r->started = true;
+                    r->t_start = clk::now();
+                }
+                rr = it;
+                return r;
+            }
+        }
+        return nullptr;
+    }
+
+    void complete_if_done(Request *r) {
+        // called with m held
+        bool over = r->running == 0 && (r->finished >= r->n || r->status != TNS_OK || r->cancel);
+        if (!over) return;
+        active.remove(r);
+        if (rr != active.end() && std::find(active.begin(), active.end(), *rr) == active.end())
+            rr = active.begin();
+        {
+            std::lock_guard<std::mutex> lk(r->m);
+            if (r->cancel && r->status == TNS_OK && r->finished < r->n) {
+                r->status = TNS_E_CANCELLED;
+                r->error = "request cancelled";
+            }
+            r->t_end = clk::now();
+            r->done = true;
+        }
+        r->cv.notify_all();
+    }
+
+    void loop(int wi) {
+        (void)hipSetDevice(ctx->device);
+        for (;;) {
+            Request *r = nullptr;
+            int64_t b0 = 0, b1 = 0;
+            {
+                std::unique_lock<std::mutex> lk(m);
+                cv.wait(lk, [&] { return stop || (r = pick(b0, b1)) != nullptr; });
+                if (!r) return;
+            }
+            tns_status st = TNS_OK;
+            std::string err;
+            RunStats rs;
+            try {
+                run_amplitudes(ctx, *r->plan, b1 - b0, r->bits + b0 * r->plan->circ.n, r->amps + 2 * b0,
+                               streams[wi], ws[wi], rs, &r->cancel, worker_budget);
+            } catch (const Error &e) {
+                st = e.code;
+                err = e.what();
+            } catch (const std::exception &e) {
+                st = TNS_E_DEVICE;
+                err = e.what();
+            }
+            if (st != TNS_OK) finish(r, st, err);
+            {
+                std::lock_guard<std::mutex> lk(m);
+                r->running--;
+                if (st == TNS_OK) r->finished += b1 - b0;
+                complete_if_done(r);
+            }
+            cv.notify_all();
+        }
+    }
+
+    void submit(Request *r) {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            active.push_back(r);
+        }
+        cv.notify_all();
+    }
+
+    void cancel(Request *r) {
+        std::lock_guard<std::mutex> lk(m);
+        r->cancel = 1;
+        complete_if_done(r);
+    }
+};
+
+}  // namespace tns
+
+using namespace tns;
+
+struct tns_ctx : public Ctx {};
+struct tns_plan : public Plan {};
+struct tns_request : public Request {};
+
+extern "C" {
+
+const char *tns_last_error(void) { return g_last_error.c_str(); }
+const char *tns_version(void) { return "tns-amp 0.1 (gfx950)"; }
+
+tns_status tns_init(int device, uint64_t hbm_budget_bytes, tns_ctx **out) {
+    return guard([&] {
+        if (!out) fail(TNS_E_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (device < -1) fail(TNS_E_INVALID_ARG, "device must be >= -1");
+        std::unique_ptr<tns_ctx> c(new tns_ctx());
+        c->device = device;
+        if (device >= 0) {
+            int count = 0;
+            hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+            if (device >= count) fail(TNS_E_INVALID_ARG, "no such device");
+            hip_check(hipSetDevice(device), "hipSetDevice");
+            hipStream_t s;
+            hip_check(hipStreamCreate(&s), "hipStreamCreate");
+            c->stream = s;
+            size_t free_b = 0, total_b = 0;
+            hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+            c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+        } else {
+            c->budget = hbm_budget_bytes;
+        }
+        *out = c.release();
+    });
+}
+
+tns_status tns_set_allocator(tns_ctx *ctx, void *(*alloc)(size_t, void *, void *),
+                             void (*free_)(void *, void *, void *), void *user) {
+    return guard([&] {
+        if (!ctx) fail(TNS_E_INVALID_ARG, "ctx is NULL");
+        if ((alloc == nullptr) != (free_ == nullptr))
+            fail(TNS_E_INVALID_ARG, "alloc and free must both be set or both be NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!ctx->ws.bufs.empty() || ctx->server)
+            fail(TNS_E_INVALID_ARG, "allocator must be installed before any device memory is used");
+        ctx->alloc_fn = alloc;
+        ctx->free_fn = free_;
+        ctx->alloc_user = user;
+    });
+}
+
+tns_status tns_finalize(tns_ctx *ctx) {
+    return guard([&] {
+        if (!ctx) return;
+        if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+        if (ctx->server) {
+            ctx->server->shutdown();
+            delete ctx->server;
+            ctx->server = nullptr;
+        }
+        if (ctx->device >= 0) {
+            ctx->ws.release(ctx, ctx->stream);
+            (void)hipStreamDestroy((hipStream_t)ctx->stream);
+        }
+        delete ctx;
+    });
+}
+
+void tns_plan_opts_default(tns_plan_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->split_cycle = -1;
+    o->path = nullptr;
+    o->path_mode = TNS_PATH_ALGORITHM1;
+    o->max_rank = 0;
+    o->path_assumptions = 1;
+    o->n_cuts = -1;
+    o->cut_edges = nullptr;
+    o->max_intermediate_elems = 1ULL << 32;
+    o->svd_rel_cutoff = 1e-12;
+    o->max_search_states = 0;
+    o->precision = TNS_C128;
+    o->n_open = 0;
+    o->open_qubits = nullptr;
+}
+
+tns_status tns_plan_create(tns_ctx *ctx, const tns_circuit_desc *desc, const tns_plan_opts *opts,
+                           tns_plan **out) {
+    return guard([&] {
+        if (!ctx || !out) fail(TNS_E_INVALID_ARG, "ctx or out is NULL");
+        *out = nullptr;
+        tns_plan_opts o;
+        if (opts) o = *opts; else tns_plan_opts_default(&o);
+        if (o.path_mode != TNS_PATH_GREEDY && o.path_mode != TNS_PATH_ALGORITHM1)
+            fail(TNS_E_INVALID_ARG, "unknown path_mode");
+        if (o.max_rank < 0 || o.max_search_states < 0) fail(TNS_E_INVALID_ARG, "negative search limit");
+        if (o.svd_rel_cutoff < 0) fail(TNS_E_INVALID_ARG, "negative svd_rel_cutoff");
+        if (o.n_cuts < -1) fail(TNS_E_INVALID_ARG, "n_cuts must be >= -1");
+        Circuit c;
+        validate_and_build(desc, c);
+        if (o.split_cycle > c.max_cycle + 1) fail(TNS_E_INVALID_ARG, "split_cycle beyond the last cycle");
+        std::unique_ptr<tns_plan> p(new tns_plan());
+        plan_host(c, o, *p);
+        if (ctx->device >= 0) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            const uint64_t need = p->bytes_per_bitstring + p->bytes_per_unit;
+            if (ctx->budget && need > ctx->budget)
+                fail(TNS_E_OUT_OF_MEMORY, "one bitstring needs " + std::to_string(need) +
+                                              " bytes of workspace, budget is " + std::to_string(ctx->budget));
+            plan_device_setup(ctx, *p);
+        }
+        *out = p.release();
+    });
+}
+
+tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
+    return guard([&] {
+        if (!p || !o) fail(TNS_E_INVALID_ARG, "NULL argument");
+        std::memset(o, 0, sizeof(*o));
+        o->n_qubits = p->circ.n;
+        o->n_edges = (int32_t)p->circ.g.edges.size();
+        o->split_cycle = p->split;
+        o->n_steps = (int32_t)p->info_m.size();
+        o->path = p->info_path.data();
+        o->step_m = p->info_m.data();
+        o->step_k = p->info_k.data();
+        o->step_n = p->info_n.data();
+        o->step_kernel = p->info_kernel.data();
+        o->step_permute = p->info_permute.data();
+        o->bond_ket = p->ket.bond.data();
+        o->bond_bra = p->bra.bond.data();
+        o->bond_overlap = p->bond_overlap.data();
+        o->n_cuts = (int32_t)p->cuts.size();
+        o->cut_edges = p->cuts.data();
+        o->n_slices = p->n_slices;
+        o->flops_per_amp = p->flops_per_amp;
+        o->gemm_bytes_per_amp = p->gemm_bytes_per_amp;
+        o->permute_bytes_per_amp = p->permute_bytes_per_amp;
+        o->path_score = p->path_score;
+        o->peak_elems = p->peak_elems;
+        o->device_bytes_resident = p->resident_bytes;
+        o->device_bytes_per_unit = p->bytes_per_unit;
+        o->n_fused_ket = p->n_fused_ket;
+        o->n_fused_bra = p->n_fused_bra;
+        o->search_complete = p->path.complete ? 1 : 0;
+        o->search_states = p->path.states;
+        o->max_rank_used = p->path.max_rank;
+        o->fidelity = p->fidelity;
+        o->n_samples = p->n_samples;
+        o->precision = (tns_precision)p->precision;
+    });
+}
+
+tns_status tns_plan_destroy(tns_plan *p) {
+    return guard([&] {
+        if (!p) return;
+        if (p->ctx && p->ctx->device >= 0) (void)hipSetDevice(p->ctx->device);
+        plan_device_release(*p);
+        delete p;
+    });
+}
+
+tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
+                          double *amps, void *hip_stream, tns_stats *stats) {
+    return guard([&] {
+        auto t0 = clk::now();
+        if (!ctx || !plan) fail(TNS_E_INVALID_ARG, "ctx or plan is NULL");
+        if (n < 0) fail(TNS_E_INVALID_ARG, "n must be >= 0");
+        if (n > 0 && (!bits || !amps)) fail(TNS_E_INVALID_ARG, "bits or amps is NULL");
+        if (ctx->device < 0) fail(TNS_E_NO_DEVICE, "planning-only context cannot compute amplitudes");
+        if (!plan->on_device || plan->ctx != ctx) fail(TNS_E_INVALID_ARG, "plan was not created on this context");
+        for (int64_t i = 0; i < n * plan->circ.n; ++i)
+            if (bits[i] > 1) fail(TNS_E_INVALID_ARG, "bits must be 0 or 1");
+        RunStats rs;
+        rs.profile = stats != nullptr;
+        if (n > 0) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            void *st = hip_stream ? hip_stream : ctx->stream;
+            run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, ctx->budget);
+        }
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+            stats->ms_bra = rs.ms_bra;
+            stats->ms_merge = rs.ms_merge;
+            stats->ms_contract = rs.ms_contract;
+            stats->flops = rs.flops;
+            stats->units = rs.units;
+            stats->launches = rs.launches;
+            stats->peak_device_bytes = ctx->peak_bytes;
+            stats->ms_gemm = rs.ms_gemm;
+            stats->gemm_launches = rs.gemm_launches;
+            stats->gemm_flops = rs.gemm_flops;
+            stats->gemm_bytes = rs.gemm_bytes;
+            stats->ms_permute = rs.ms_permute;
+            stats->permute_bytes = rs.permute_bytes;
+            stats->ms_small = rs.ms_small;
+        }
+    });
+}
+
+tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
+                      double *amps, tns_request **out) {
+    return guard([&] {
+        if (!ctx || !plan || !out) fail(TNS_E_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        if (n < 0) fail(TNS_E_INVALID_ARG, "n must be >= 0");
+        if (n > 0 && (!bits || !amps)) fail(TNS_E_INVALID_ARG, "bits or amps is NULL");
+        if (ctx->device < 0) fail(TNS_E_NO_DEVICE, "planning-only context cannot serve");
+        if (!plan->on_device || plan->ctx != ctx) fail(TNS_E_INVALID_ARG, "plan was not created on this context");
+        for (int64_t i = 0; i < n * plan->circ.n; ++i)
+            if (bits[i] > 1) fail(TNS_E_INVALID_ARG, "bits must be 0 or 1");
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            if (!ctx->server) {
+                ctx->server = new Server();
+                ctx->server->start(ctx, 3);
+            }
+        }
+        Server *sv = ctx->server;
+        const uint64_t need = plan->bytes_per_bitstring + plan->bytes_per_unit;
+        if (need > sv->worker_budget)
+            fail(TNS_E_ADMISSION, "request needs " + std::to_string(need) + " bytes per chunk, a serving slot has " +
+                                      std::to_string(sv->worker_budget));
+        std::unique_ptr<tns_request> r(new tns_request());
+        r->plan = plan;
+        r->n = n;
+        r->bits = bits;
+        r->amps = amps;
+        int64_t fit = max_bitstrings_per_batch(ctx, *plan, sv->worker_budget);
+        r->chunk = std::max<int64_t>(1, std::min<int64_t>(fit, 64));
+        r->t_submit = clk::now();
+        if (n == 0) {
+            r->done = true;
+            r->t_start = r->t_end = r->t_submit;
+            *out = r.release();
+            return;
+        }
+        tns_request *raw = r.release();
+        sv->submit(raw);
+        *out = raw;
+    });
+}
+
+tns_status tns_poll(tns_request *r, int *done) {
+    return guard([&] {
+        if (!r || !done) fail(TNS_E_INVALID_ARG, "NULL argument");
+        std::lock_guard<std::mutex> lk(r->m);
+        *done = r->done ? 1 : 0;
+    });
+}
+
+tns_status tns_wait(tns_request *r) {
+    if (!r) {
+        set_last_error("request is NULL");
+        return TNS_E_INVALID_ARG;
+    }
+    std::unique_lock<std::mutex> lk(r->m);
+    r->cv.wait(lk, [&] { return r->done; });
+    if (r->status != TNS_OK) set_last_error(r->error);
+    return r->status;
+}
+
+tns_status tns_cancel(tns_request *r) {
+    return guard([&] {
+        if (!r) fail(TNS_E_INVALID_ARG, "request is NULL");
+        if (r->plan && r->plan->ctx && r->plan->ctx->server) r->plan->ctx->server->cancel(r);
+        else r->cancel = 1;
+    });
+}
+
+tns_status tns_request_free(tns_request *r) {
+    if (!r) return TNS_OK;
+    (void)tns_wait(r);
+    delete r;
+    return TNS_OK;
+}
+
+tns_status tns_request_latency(const tns_request *r, double *ms_total, double *ms_run) {
+    return guard([&] {
+        if (!r) fail(TNS_E_INVALID_ARG, "request is NULL");
+        auto *rr = const_cast<tns_request *>(r);
+        std::lock_guard<std::mutex> lk(rr->m);
+        if (!r->done) fail(TNS_E_INVALID_ARG, "request not finished");
+        if (ms_total) *ms_total = std::chrono::duration<double, std::milli>(r->t_end - r->t_submit).count();
+        if (ms_run) *ms_run = std::chrono::duration<double, std::milli>(r->t_end - r->t_start).count();
+    });
+}
+
+tns_status tns_path_search(int32_t n, int32_t n_edges, const int32_t *edges, const double *dims,
+                           int32_t mode, int32_t max_rank, int32_t assumptions, int64_t max_states,
+                           int32_t *path_out, double *score_out) {
+    return guard([&] {
+        if (n < 1 || n > TNS_MAX_QUBITS) fail(TNS_E_INVALID_ARG, "n out of range");
+        if (n_edges < 0 || (n_edges > 0 && (!edges || !dims)) || !path_out)
+            fail(TNS_E_INVALID_ARG, "NULL argument");
+        std::vector<std::pair<int, int>> E;
+        std::vector<double> D;
+        for (int e = 0; e < n_edges; ++e) {
+            int a = edges[2 * e], b = edges[2 * e + 1];
+            if (a < 0 || b < 0 || a >= n || b >= n || a == b) fail(TNS_E_INVALID_ARG, "bad edge");
+            if (!(dims[e] >= 1.0)) fail(TNS_E_INVALID_ARG, "bond dimensions must be >= 1");
+            E.push_back({a, b});
+            D.push_back(dims[e]);
+        }
+        if (mode != TNS_PATH_GREEDY && mode != TNS_PATH_ALGORITHM1) fail(TNS_E_INVALID_ARG, "unknown mode");
+        PathResult r = path_search(n, E, D, mode, max_rank, assumptions != 0, max_states);
+        for (int i = 0; i < n; ++i) path_out[i] = r.order[i];
+        if (score_out) *score_out = r.score;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+// Internal declarations of the tensor-network-states amplitude library.
+// Host planning structures, device launch descriptors and the launcher
+// prototypes shared by the host code and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tns.h"
+
+namespace tns {
+
+// ----------------------------------------------------------------------------
+// errors
+
+struct Error : std::runtime_error {
+    tns_status code;
+    Error(tns_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(tns_status code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+// ----------------------------------------------------------------------------
+// limits
+
+constexpr int kMaxDeg = TNS_MAX_DEGREE;   // legs per site
+constexpr int kMaxGatherDims = 24;        // axes of one strided gather / permute
+constexpr int kMaxChi = 4;                // two-qubit operator Schmidt rank
+
+// ----------------------------------------------------------------------------
+// device launch descriptors (passed by value to kernels)
+
+// Shape of a site tensor during the evolution: n axes, axis 0 the physical
+// leg (2), then the site's bonds in edge-id order.
+struct SiteShape {
+    int32_t n;
+    int32_t d[kMaxDeg + 1];
+};
+
+// Strided gather: out[i] = in[base + sum_a idx_a(i) * stride[a]] with i the
+// row-major index over size[0..n).  Used for permutes, the initial boundary
+// tensor and the B operand of each step.
+struct Gather {
+    int32_t n;
+    int64_t size[kMaxGatherDims];
+    int64_t stride[kMaxGatherDims];
+};
+
+// Offset of one slice inside a site tensor: the slice index is a mixed-radix
+// number over the cut bonds (last cut fastest); only the cut bonds that touch
+// the site contribute, each with its stride in the site tensor.
+constexpr int kMaxCuts = 24;
+struct SliceMap {
+    int32_t n;
+    int64_t div[kMaxCuts];
+    int64_t dim[kMaxCuts];
+    int64_t stride[kMaxCuts];
+};
+
+// One fused two-qubit operation for the fuse/split kernel.
+struct FuseDesc {
+    int32_t gate;        // base two-qubit gate (index into the circuit's gates)
+    int32_t pre0, pre1;  // chains applied before the gate on q0 / q1 (-1: none)
+    int32_t post0, post1;// chains applied after the gate (-1: none)
+    int32_t transpose;   // split the transpose (bra side)
+    int32_t chi;         // number of singular triplets to keep
+    int32_t pad;
+};
+
+// ----------------------------------------------------------------------------
+// host planning structures
+
+struct Graph {
+    int n = 0;
+    std::vector<std::pair<int, int>> edges;
+    std::vector<std::vector<int>> legs;   // per site, incident edge ids ascending
+    std::map<std::pair<int, int>, int> index;
+    int edge_id(int a, int b) const {
+        auto it = index.find({a < b ? a : b, a < b ? b : a});
+        return it == index.end() ? -1 : it->second;
+    }
+    int leg_of(int site, int edge) const {
+        for (size_t i = 0; i < legs[site].size(); ++i)
+            if (legs[site][i] == edge) return (int)i;
+        return -1;
+    }
+};
+
+// A fused two-qubit operation as applied on one side of the evolution.
+struct EvoOp {
+    int fused;           // index into the fuse descriptors (P/Q storage slot)
+    int q0, q1, edge, chi;
+    int leg0, leg1;      // position of `edge` among the bonds of q0 / q1
+    SiteShape s0, s1;    // shapes of the two sites before the op
+    int d_before, d_grown, d_after;
+    int comp;            // -1: no compression; 0: SVD on q0, absorb into q1; 1: reverse
+};
+
+struct SideEvolution {
+    std::vector<EvoOp> ops;              // in application order
+    std::vector<int> bond;               // final bond dims per edge
+    std::vector<int64_t> cap;            // per-site buffer capacity (elements)
+    std::vector<SiteShape> final_shape;  // per-site shape at the end
+};
+
+// One pairwise contraction step (supplement, Eq. for C^{i_1..i_m}).
+struct Step {
+    int site = -1;                       // tensor absorbed (i_{m+1}); for step 0 the start
+    std::vector<int> t_legs;             // boundary legs before the step (storage order)
+    bool permute = false;
+    Gather perm;                         // boundary permute (t_legs -> m_legs ++ k_legs)
+    std::vector<int> m_legs, k_legs, n_legs;
+    int64_t M = 1, K = 1, N = 1;
+    int kernel = 0;                      // 0 MFMA GEMM, 1 small, 2 final dot
+    Gather bgather;                      // site tensor -> B[n][k] (k fastest)
+    int64_t out_elems = 0;               // M * N
+};
+
+struct Plan;
+
+// ----------------------------------------------------------------------------
+// host planner entry points (planner.cpp)
+
+struct Circuit {
+    int n = 0;
+    Graph g;
+    std::vector<tns_gate> gates;
+    int max_cycle = 0;
+};
+
+void validate_and_build(const tns_circuit_desc *desc, Circuit &c);
+int operator_schmidt_rank(const double *m32);
+
+struct PathResult {
+    std::vector<int> order;
+    double score = 0;
+    double peak = 0;
+    int max_rank = 0;
+    int64_t states = 0;
+    bool complete = true;
+};
+
+PathResult path_search(int n, const std::vector<std::pair<int, int>> &edges,
+                       const std::vector<double> &dims, int mode, int max_rank,
+                       bool assumptions, int64_t max_states);
+double path_score(int n, const std::vector<std::pair<int, int>> &edges,
+                  const std::vector<double> &dims, const std::vector<int> &order,
+                  double *peak, int *max_rank);
+
+void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p);
+
+// ----------------------------------------------------------------------------
+// the plan
+
+struct DeviceBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Ctx;
+
+struct Plan {
+    // inputs
+    Circuit circ;
+    tns_plan_opts opts{};
+    int split = 0;
+    int precision = TNS_C128;
+
+    // fusion
+    std::vector<FuseDesc> fuse;          // ket ops first, then bra ops
+    std::vector<int32_t> chain_flat;     // gate indices
+    std::vector<int32_t> chain_off, chain_len;
+    std::vector<int32_t> ket_init_chain, bra_final_chain;  // per qubit, -1: identity
+    int n_fused_ket = 0, n_fused_bra = 0;
+
+    SideEvolution ket, bra;
+    std::vector<int> bond_overlap;
+
+    // slicing
+    std::vector<int> cuts;
+    int64_t n_slices = 1;
+    std::vector<int64_t> slice_radix;    // dims of the cut bonds
+
+    // overlap site tensors: physical layout = bonds in edge-id order
+    std::vector<std::vector<int64_t>> site_dims;   // per site, overlap dims per bond
+    std::vector<int64_t> site_elems;
+
+    // path and steps
+    PathResult path;
+    std::vector<Step> steps;
+    int64_t peak_elems = 0;
+    int64_t unit_stride = 0;             // boundary buffer stride per unit (peak, 32-aligned)
+    int64_t max_b_elems = 0;             // largest B operand (complex elements)
+    double flops_per_amp = 0, gemm_bytes_per_amp = 0, permute_bytes_per_amp = 0;
+    double path_score = 0;
+
+    // per-site slice offsets of the cut bonds
+    std::vector<SliceMap> slice_map;
+
+    // info arrays exposed through tns_plan_info
+    std::vector<int64_t> info_m, info_k, info_n;
+    std::vector<int32_t> info_kernel, info_permute, info_path;
+    double fidelity = 0, n_samples = 0;
+
+    // device state
+    Ctx *ctx = nullptr;
+    bool on_device = false;
+    DeviceBuf d_mats, d_chain, d_chain_off, d_chain_len, d_fuse, d_pq;
+    DeviceBuf d_ket_vec, d_bra_mat;
+    std::vector<DeviceBuf> ket_site;     // resident ket tensors (complex128)
+    int64_t resident_bytes = 0;
+    int64_t bytes_per_unit = 0;
+    int64_t bytes_per_bitstring = 0;
+    int64_t bra_scratch_elems = 0;       // V' scratch per bitstring (complex128)
+};
+
+// ----------------------------------------------------------------------------
+// runtime context
+
+struct Ctx;
+
+// Workspace buffers owned by one executor (the synchronous path or one
+// serving stream); grown on demand, reused across calls.
+struct Workspace {
+    std::vector<DeviceBuf> bufs;
+    int64_t bytes = 0;
+    void *get(Ctx *ctx, int slot, size_t bytes, void *stream);
+    void release(Ctx *ctx, void *stream);
+};
+
+struct Server;
+
+struct Ctx {
+    int device = -1;
+    uint64_t budget = 0;
+    void *stream = nullptr;              // hipStream_t
+    void *(*alloc_fn)(size_t, void *, void *) = nullptr;
+    void (*free_fn)(void *, void *, void *) = nullptr;
+    void *alloc_user = nullptr;
+    std::mutex mu;                       // serialises synchronous calls
+    std::mutex mu_stats;
+    Workspace ws;                        // workspace of synchronous calls
+    int64_t peak_bytes = 0;
+    Server *server = nullptr;
+};
+
+void *dev_alloc(Ctx *ctx, size_t bytes, void *stream);
+void dev_free(Ctx *ctx, void *p, void *stream);
+
+void plan_device_setup(Ctx *ctx, Plan &p);
+void plan_device_release(Plan &p);
+
+struct RunStats {
+    double ms_bra = 0, ms_merge = 0, ms_contract = 0;
+    double flops = 0;
+    int64_t units = 0, launches = 0;
+    bool profile = false;            // time kernel classes with events
+    double ms_gemm = 0, gemm_flops = 0, gemm_bytes = 0;
+    int64_t gemm_launches = 0;
+    double ms_permute = 0, permute_bytes = 0, ms_small = 0;
+};
+
+// Amplitudes of bitstrings [0, n) into host amps (complex128 pairs), using at
+// most `budget` bytes of workspace beyond the plan's resident tensors.
+void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
+                    double *amps_host, void *stream, Workspace &ws, RunStats &st,
+                    const volatile int *cancel, uint64_t budget);
+int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
+
+// ----------------------------------------------------------------------------
+// kernel launchers (kernels_*.hip).  All take a hipStream_t as void*.
+
+namespace launch {
+void fuse_split(const double *mats, const int32_t *chain, const int32_t *chain_off,
+                const int32_t *chain_len, const FuseDesc *fuse, int n_fuse,
+                double *pq, int n_qubits, const int32_t *ket_chain,
+                const int32_t *bra_chain, double *ket_vec, double *bra_mat, void *stream);
+void init_ket(const double *ket_vec, int q, double *site, void *stream);
+void init_bra(const uint8_t *bits, int n_qubits, int64_t nb, int q, const double *bra_mat,
+              double *site, int64_t stride, void *stream);
+void gate_apply(const double *in, double *out, int64_t nb, int64_t in_stride,
+                int64_t out_stride, SiteShape s, int leg, int chi, const double *g,
+                void *stream);
+void svd_compress(const double *in, double *out_site, double *vp, int64_t nb,
+                  int64_t in_stride, int64_t out_stride, int64_t vp_stride, SiteShape s,
+                  int leg, void *stream);
+void absorb(const double *in, const double *vp, double *out, int64_t nb, int64_t in_stride,
+            int64_t vp_stride, int64_t out_stride, SiteShape s, int leg, int r,
+            void *stream);
+void merge(const double *ket, const double *bra, void *out, int64_t nb, int64_t bra_stride,
+           int64_t out_stride, SiteShape sk, SiteShape sb, int c64, void *stream);
+
+void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
+            int64_t out_unit_stride, const Gather &g, int elem_bytes, void *stream);
+void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
+                 int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
+                 const Gather &g, int elem_bytes, void *stream);
+void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
+             int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
+             int64_t N, int c64, int embed, void *stream);
+void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64, void *stream);
+void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
+                    int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
+                    void *stream);
+void final_dot(const void *A, const void *Bt, double *partial, int64_t units, int64_t K,
+               int64_t sA, int64_t sB, int c64, void *stream);
+void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices,
+               void *stream);
+}  // namespace launch
+
+}  // namespace tns

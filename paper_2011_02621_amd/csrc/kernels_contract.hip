@@ -1,0 +1,496 @@
+// Contraction-side kernels (supplement: C^{i_1..i_{m+1}} = contract(C^{i_1..i_m},
+// C^{i_{m+1}}), one pairwise step at a time):
+//   gather / gather_site -- strided copies: boundary permutes, the starting
+//                           tensor, slice selection of cut bonds
+//   build_b              -- the site tensor as B[n][k] (k fastest), either plain
+//                           complex or as the real embedding of a complex matrix
+//   gemm                 -- complex GEMM T'[M,N] = T[M,K] B[K,N] as one real GEMM
+//                           [M,2K] x [2K,2N] on the MFMA cores (4 real products):
+//                           complex64 on FP32 MFMA, complex128 on FP64 MFMA
+//   small_contract       -- thread-per-output contraction for small K or N
+//   final_dot            -- last step (scalar): widened to FP64
+//   slice_sum            -- FP64 sum of the slices of each bitstring (overlap
+//                           paragraph: the sub-network scalars add up)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace tns {
+namespace {
+
+inline unsigned grid_for(int64_t total, int threads) {
+    int64_t g = (total + threads - 1) / threads;
+    if (g > 65536 * 4) g = 65536 * 4;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+inline void check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(TNS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__device__ __forceinline__ int64_t slice_offset(const SliceMap &sm, int64_t s) {
+    int64_t off = 0;
+    for (int c = 0; c < sm.n; ++c) off += ((s / sm.div[c]) % sm.dim[c]) * sm.stride[c];
+    return off;
+}
+
+__device__ __forceinline__ int64_t gather_offset(const Gather &g, int64_t i) {
+    int64_t off = 0;
+    for (int a = g.n - 1; a >= 0; --a) {
+        const int64_t s = g.size[a];
+        const int64_t q = i / s;
+        off += (i - q * s) * g.stride[a];
+        i = q;
+    }
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// strided gathers.  E is the complex element (float2 or double2).
+
+template <typename E>
+__global__ void k_gather(const E *__restrict__ in, E *__restrict__ out, int64_t units,
+                         int64_t in_us, int64_t out_us, Gather g, int64_t per) {
+    const int64_t total = per * units;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / per, i = t - u * per;
+        out[u * out_us + i] = in[u * in_us + gather_offset(g, i)];
+    }
+}
+
+// unit u of this launch is global unit ug = u0 + u = bitstring * n_slices + slice
+template <typename E>
+__global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, int64_t units,
+                              int64_t u0, int64_t n_slices, int64_t site_stride,
+                              SliceMap sm, int64_t out_us, Gather g,
+                              int64_t per) {
+    const int64_t total = per * units;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / per, i = t - u * per;
+        const int64_t ug = u0 + u;
+        const int64_t b = ug / n_slices, s = ug - b * n_slices;
+        const int64_t base = b * site_stride + slice_offset(sm, s);
+        out[u * out_us + i] = site[base + gather_offset(g, i)];
+    }
+}
+
+// B[n][k] from the site tensor; with embed, the real matrix Bt[2N][2K]
+// (k fastest) whose product with the interleaved [M][2K] view of T yields the
+// interleaved complex result [M][2N]:
+//   Bt[2n][2k] = Re b, Bt[2n][2k+1] = -Im b, Bt[2n+1][2k] = Im b, Bt[2n+1][2k+1] = Re b.
+template <typename R>
+__global__ void k_build_b(const R *__restrict__ site, R *__restrict__ out, int64_t units,
+                          int64_t u0, int64_t n_slices, int64_t site_stride,
+                          SliceMap sm, Gather g, int64_t K, int64_t N,
+                          int embed) {
+    const int64_t per = K * N;
+    const int64_t total = per * units;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / per, i = t - u * per;
+        const int64_t ug = u0 + u;
+        const int64_t b = ug / n_slices, s = ug - b * n_slices;
+        const int64_t src = b * site_stride + slice_offset(sm, s) + gather_offset(g, i);
+        const R re = site[2 * src], im = site[2 * src + 1];
+        if (!embed) {
+            out[2 * (u * per + i)] = re;
+            out[2 * (u * per + i) + 1] = im;
+        } else {
+            const int64_t n = i / K, k = i - n * K;
+            R *o = out + u * 4 * per;
+            const int64_t ld = 2 * K;
+            o[(2 * n) * ld + 2 * k] = re;
+            o[(2 * n) * ld + 2 * k + 1] = -im;
+            o[(2 * n + 1) * ld + 2 * k] = im;
+            o[(2 * n + 1) * ld + 2 * k + 1] = re;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 MFMA GEMM: C[M][Nr] = A[M][Kr] * Bt[Nr][Kr]^T, all row-major, Kr % 4 == 0.
+// 256 threads, tile 128 x 128, k-step 32.  Four waves in a 2 x 2 layout, each
+// owning 64 x 64 as 2 x 2 blocks of v_mfma_f32_32x32x2f32.  The two k-slots
+// of one MFMA (lanes 0-31 / 32-63) are mapped to k = 4*slot + t for the four
+// MFMAs t = 0..3 of an 8-wide k group, so each lane reads its four A (and B)
+// values with one 16-byte LDS load.
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+constexpr int F32_BM = 128, F32_BN = 128, F32_BK = 32, F32_LD = F32_BK + 4;
+
+__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A,
+                                                   const float *__restrict__ Bt,
+                                                   float *__restrict__ C, int64_t M, int Kr,
+                                                   int Nr, int64_t sA, int64_t sB, int64_t sC,
+                                                   int tiles_n) {
+    __shared__ float As[F32_BM * F32_LD];
+    __shared__ float Bs[F32_BN * F32_LD];
+    const int64_t u = blockIdx.y;
+    const int64_t tile = blockIdx.x;
+    const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+    const int64_t m0 = tm * F32_BM;
+    const int n0 = (int)tn * F32_BN;
+    A += u * sA;
+    Bt += u * sB;
+    C += u * sC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    v16f acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int lrow = tid >> 3, lcol = (tid & 7) * 4;
+    for (int k0 = 0; k0 < Kr; k0 += F32_BK) {
+        const int gk = k0 + lcol;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = lrow + 32 * i;
+            const int64_t gm = m0 + row;
+            v4f va = {0.f, 0.f, 0.f, 0.f};
+            if (gm < M && gk < Kr) va = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
+            *reinterpret_cast<v4f *>(&As[row * F32_LD + lcol]) = va;
+            const int gn = n0 + row;
+            v4f vb = {0.f, 0.f, 0.f, 0.f};
+            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
+            *reinterpret_cast<v4f *>(&Bs[row * F32_LD + lcol]) = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < F32_BK; kk += 8) {
+            const int kofs = kk + 4 * (lane >> 5);
+            v4f a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const v4f *>(&As[(wm * 64 + i * 32 + (lane & 31)) * F32_LD + kofs]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const v4f *>(&Bs[(wn * 64 + j * 32 + (lane & 31)) * F32_LD + kofs]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // 32x32 accumulator layout: lane holds column lane%32 and rows
+    // 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+            }
+}
+
+// FP64 MFMA GEMM with v_mfma_f64_16x16x4f64: tile 64 x 64, k-step 16, four
+// waves in 2 x 2, each 32 x 32 as 2 x 2 blocks of 16 x 16.  The four k-slots
+// (lanes 16*slot .. 16*slot+15) map to k = 4*slot + t for the four MFMAs of a
+// 16-wide k group.
+constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16, F64_LD = F64_BK + 2;
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
+                                                   const double *__restrict__ Bt,
+                                                   double *__restrict__ C, int64_t M, int Kr,
+                                                   int Nr, int64_t sA, int64_t sB, int64_t sC,
+                                                   int tiles_n) {
+    __shared__ double As[F64_BM * F64_LD];
+    __shared__ double Bs[F64_BN * F64_LD];
+    const int64_t u = blockIdx.y;
+    const int64_t tile = blockIdx.x;
+    const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+    const int64_t m0 = tm * F64_BM;
+    const int n0 = (int)tn * F64_BN;
+    A += u * sA;
+    Bt += u * sB;
+    C += u * sC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    v4d acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+    const int lrow = tid >> 2, lcol = (tid & 3) * 4;
+    for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gk = k0 + lcol + 2 * h;
+            const int64_t gm = m0 + lrow;
+            v2d va = {0.0, 0.0};
+            if (gm < M && gk < Kr) va = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
+            *reinterpret_cast<v2d *>(&As[lrow * F64_LD + lcol + 2 * h]) = va;
+            const int gn = n0 + lrow;
+            v2d vb = {0.0, 0.0};
+            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
+            *reinterpret_cast<v2d *>(&Bs[lrow * F64_LD + lcol + 2 * h]) = vb;
+        }
+        __syncthreads();
+        const int kofs = 4 * (lane >> 4);
+        v4d a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double *p = &As[(wm * 32 + i * 16 + (lane & 15)) * F64_LD + kofs];
+            a[i] = v4d{p[0], p[1], p[2], p[3]};
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const double *p = &Bs[(wn * 32 + j * 16 + (lane & 15)) * F64_LD + kofs];
+            b[j] = v4d{p[0], p[1], p[2], p[3]};
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // 16x16 f64 accumulator layout: lane holds column lane%16 and rows 4*(lane/16) + r.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// small steps: one thread per output element, C[u][m][n] = sum_k A[u][m][k] B[u][n][k]
+
+template <typename R, typename Acc>
+__global__ void k_small(const R *__restrict__ A, const R *__restrict__ Bt, R *__restrict__ C,
+                        int64_t units, int64_t M, int64_t K, int64_t N, int64_t sA, int64_t sB,
+                        int64_t sC) {
+    const int64_t per = M * N;
+    const int64_t total = per * units;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / per, i = t - u * per;
+        const int64_t m = i / N, n = i - m * N;
+        const R *a = A + 2 * (u * sA + m * K);
+        const R *b = Bt + 2 * (u * sB + n * K);
+        Acc re = 0, im = 0;
+        for (int64_t k = 0; k < K; ++k) {
+            const Acc ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+            re += ar * br - ai * bi;
+            im += ar * bi + ai * br;
+        }
+        C[2 * (u * sC + i)] = (R)re;
+        C[2 * (u * sC + i) + 1] = (R)im;
+    }
+}
+
+// last step: one workgroup per unit, sum_k A[k] B[k] accumulated in FP64
+template <typename R>
+__global__ __launch_bounds__(256) void k_final_dot(const R *__restrict__ A,
+                                                    const R *__restrict__ Bt,
+                                                    double *__restrict__ partial, int64_t K,
+                                                    int64_t sA, int64_t sB) {
+    __shared__ double sre[256], sim[256];
+    const int64_t u = blockIdx.x;
+    const R *a = A + 2 * u * sA;
+    const R *b = Bt + 2 * u * sB;
+    double re = 0, im = 0;
+    for (int64_t k = threadIdx.x; k < K; k += 256) {
+        const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sre[threadIdx.x] += sre[threadIdx.x + w];
+            sim[threadIdx.x] += sim[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * u] = sre[0];
+        partial[2 * u + 1] = sim[0];
+    }
+}
+
+// Pairwise (binary-counter) summation of the slices of each bitstring: a
+// fixed tree, so the result does not depend on launch configuration.
+__global__ void k_slice_sum(const double *__restrict__ partial, double *__restrict__ amps,
+                            int64_t nb, int64_t n_slices) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double sr[64], si[64];
+    int lv[64];
+    int top = 0;
+    const double *x = partial + 2 * b * n_slices;
+    for (int64_t i = 0; i < n_slices; ++i) {
+        double vr = x[2 * i], vi = x[2 * i + 1];
+        int l = 0;
+        while (top > 0 && lv[top - 1] == l) {
+            vr = sr[top - 1] + vr;
+            vi = si[top - 1] + vi;
+            --top;
+            ++l;
+        }
+        sr[top] = vr;
+        si[top] = vi;
+        lv[top] = l;
+        ++top;
+    }
+    double rr = 0, ri = 0;
+    if (top > 0) {
+        rr = sr[top - 1];
+        ri = si[top - 1];
+        for (int j = top - 2; j >= 0; --j) {
+            rr = sr[j] + rr;
+            ri = si[j] + ri;
+        }
+    }
+    amps[2 * b] = rr;
+    amps[2 * b + 1] = ri;
+}
+
+}  // namespace
+
+namespace launch {
+
+void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
+            int64_t out_unit_stride, const Gather &g, int elem_bytes, void *stream) {
+    int64_t per = 1;
+    for (int a = 0; a < g.n; ++a) per *= g.size[a];
+    const int64_t total = per * units;
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_gather<float2>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const float2 *)in, (float2 *)out, units,
+                           in_unit_stride, out_unit_stride, g, per);
+    else
+        hipLaunchKernelGGL(k_gather<double2>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const double2 *)in, (double2 *)out, units,
+                           in_unit_stride, out_unit_stride, g, per);
+    check_launch("gather");
+}
+
+void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
+                 int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
+                 const Gather &g, int elem_bytes, void *stream) {
+    int64_t per = 1;
+    for (int a = 0; a < g.n; ++a) per *= g.size[a];
+    const int64_t total = per * units;
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_gather_site<float2>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const float2 *)site, (float2 *)out, units, u0,
+                           n_slices, site_stride, sm, out_unit_stride, g, per);
+    else
+        hipLaunchKernelGGL(k_gather_site<double2>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const double2 *)site, (double2 *)out, units, u0,
+                           n_slices, site_stride, sm, out_unit_stride, g, per);
+    check_launch("gather_site");
+}
+
+void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
+             int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
+             int64_t N, int c64, int embed, void *stream) {
+    const int64_t total = K * N * units;
+    if (c64)
+        hipLaunchKernelGGL(k_build_b<float>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const float *)site, (float *)out, units, u0,
+                           n_slices, site_stride, sm, g, K, N, embed);
+    else
+        hipLaunchKernelGGL(k_build_b<double>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const double *)site, (double *)out, units, u0,
+                           n_slices, site_stride, sm, g, K, N, embed);
+    check_launch("build_b");
+}
+
+void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64, void *stream) {
+    // strides arrive in complex elements; the kernels index reals
+    const int Kr = (int)(2 * K), Nr = (int)(2 * N);
+    if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
+    const int BM = c64 ? F32_BM : F64_BM, BN = c64 ? F32_BN : F64_BN;
+    const int tiles_n = (Nr + BN - 1) / BN;
+    // rows per launch so that the grid stays below 2^31 blocks
+    const int64_t max_tiles_m = ((int64_t)1 << 30) / tiles_n;
+    const int64_t rows_per = max_tiles_m * BM;
+    for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+        const int64_t nu = std::min<int64_t>(65535, units - u0);
+        for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
+            const int64_t mr = std::min<int64_t>(rows_per, M - r0);
+            const int64_t tiles_m = (mr + BM - 1) / BM;
+            const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)nu);
+            if (c64)
+                hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, (hipStream_t)stream,
+                                   (const float *)A + 2 * (u0 * sA + r0 * K),
+                                   (const float *)Bt + 4 * u0 * sB,
+                                   (float *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
+                                   2 * sC, tiles_n);
+            else
+                hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, (hipStream_t)stream,
+                                   (const double *)A + 2 * (u0 * sA + r0 * K),
+                                   (const double *)Bt + 4 * u0 * sB,
+                                   (double *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
+                                   2 * sC, tiles_n);
+            check_launch("gemm");
+        }
+    }
+}
+
+void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
+                    int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
+                    void *stream) {
+    const int64_t total = M * N * units;
+    if (c64)
+        hipLaunchKernelGGL((k_small<float, float>), dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const float *)A, (const float *)Bt, (float *)C,
+                           units, M, K, N, sA, sB, sC);
+    else
+        hipLaunchKernelGGL((k_small<double, double>), dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const double *)A, (const double *)Bt, (double *)C,
+                           units, M, K, N, sA, sB, sC);
+    check_launch("small_contract");
+}
+
+void final_dot(const void *A, const void *Bt, double *partial, int64_t units, int64_t K,
+               int64_t sA, int64_t sB, int c64, void *stream) {
+    for (int64_t u0 = 0; u0 < units; u0 += 1 << 30) {
+        const int64_t nu = std::min<int64_t>(1 << 30, units - u0);
+        if (c64)
+            hipLaunchKernelGGL(k_final_dot<float>, dim3((unsigned)nu), dim3(256), 0,
+                               (hipStream_t)stream, (const float *)A + 2 * u0 * sA,
+                               (const float *)Bt + 2 * u0 * sB, partial + 2 * u0, K, sA, sB);
+        else
+            hipLaunchKernelGGL(k_final_dot<double>, dim3((unsigned)nu), dim3(256), 0,
+                               (hipStream_t)stream, (const double *)A + 2 * u0 * sA,
+                               (const double *)Bt + 2 * u0 * sB, partial + 2 * u0, K, sA, sB);
+        check_launch("final_dot");
+    }
+}
+
+void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices, void *stream) {
+    hipLaunchKernelGGL(k_slice_sum, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0,
+                       (hipStream_t)stream, partial, amps, nb, n_slices);
+    check_launch("slice_sum");
+}
+
+}  // namespace launch
+}  // namespace tns

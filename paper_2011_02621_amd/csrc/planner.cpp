@@ -1,0 +1,1003 @@
+// Host planning: everything that decides shapes, orders and launch
+// descriptors.  No amplitude arithmetic happens here; the device kernels do
+// all of it.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <functional>
+#include <limits>
+#include <numeric>
+#include <queue>
+#include <unordered_set>
+
+#include "internal.h"
+
+namespace tns {
+
+using cd = std::complex<double>;
+
+// ----------------------------------------------------------------------------
+// circuit validation and graph
+
+static cd gm(const tns_gate &g, int r, int c, int dim) {
+    int i = r * dim + c;
+    return cd(g.m[2 * i], g.m[2 * i + 1]);
+}
+
+static bool unitary(const tns_gate &g, int dim, double tol) {
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            cd acc = 0;
+            for (int k = 0; k < dim; ++k) acc += std::conj(gm(g, k, i, dim)) * gm(g, k, j, dim);
+            if (std::abs(acc - (i == j ? 1.0 : 0.0)) > tol) return false;
+        }
+    return true;
+}
+
+void validate_and_build(const tns_circuit_desc *desc, Circuit &c) {
+    if (!desc) fail(TNS_E_INVALID_ARG, "circuit descriptor is NULL");
+    const int n = desc->n_qubits;
+    if (n < 2 || n > TNS_MAX_QUBITS)
+        fail(TNS_E_BAD_CIRCUIT, "n_qubits must be in [2, " + std::to_string(TNS_MAX_QUBITS) + "]");
+    if (desc->n_edges < 0 || (desc->n_edges > 0 && !desc->edges))
+        fail(TNS_E_INVALID_ARG, "bad edge array");
+    if (desc->n_gates < 0 || (desc->n_gates > 0 && !desc->gates))
+        fail(TNS_E_INVALID_ARG, "bad gate array");
+    c.n = n;
+    c.g = Graph{};
+    c.g.n = n;
+    c.g.legs.assign(n, {});
+    for (int e = 0; e < desc->n_edges; ++e) {
+        int a = desc->edges[2 * e], b = desc->edges[2 * e + 1];
+        if (a < 0 || b < 0 || a >= n || b >= n || a == b)
+            fail(TNS_E_BAD_CIRCUIT, "edge " + std::to_string(e) + " has a bad endpoint");
+        std::pair<int, int> key{std::min(a, b), std::max(a, b)};
+        if (c.g.index.count(key)) fail(TNS_E_BAD_CIRCUIT, "duplicate edge " + std::to_string(e));
+        c.g.index[key] = e;
+        c.g.edges.push_back(key);
+        c.g.legs[a].push_back(e);
+        c.g.legs[b].push_back(e);
+    }
+    for (int q = 0; q < n; ++q) {
+        std::sort(c.g.legs[q].begin(), c.g.legs[q].end());
+        if ((int)c.g.legs[q].size() > kMaxDeg)
+            fail(TNS_E_UNSUPPORTED, "qubit " + std::to_string(q) + " has more than " +
+                                        std::to_string(kMaxDeg) + " couplers");
+    }
+    c.gates.assign(desc->gates, desc->gates + desc->n_gates);
+    c.max_cycle = 0;
+    for (int i = 0; i < desc->n_gates; ++i) {
+        const tns_gate &g = c.gates[i];
+        if (g.q0 < 0 || g.q0 >= n) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + ": q0 out of range");
+        if (g.cycle < 0) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + ": negative cycle");
+        c.max_cycle = std::max(c.max_cycle, g.cycle);
+        for (int k = 0; k < 32; ++k)
+            if (!std::isfinite(g.m[k])) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + ": non-finite entry");
+        if (g.q1 < 0) {
+            if (!unitary(g, 2, 1e-8)) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + " is not unitary");
+        } else {
+            if (g.q1 >= n || g.q1 == g.q0) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + ": bad q1");
+            if (c.g.edge_id(g.q0, g.q1) < 0)
+                fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + " acts on a pair that is not an edge");
+            if (!unitary(g, 4, 1e-8)) fail(TNS_E_BAD_CIRCUIT, "gate " + std::to_string(i) + " is not unitary");
+        }
+    }
+}
+
+// Operator Schmidt rank of a two-qubit gate, i.e. the number of nonzero
+// singular values of O reshaped to [(s0' s0), (s1' s1)] (Eq. (2)).  Local
+// single-qubit factors do not change it, so the rank of the base gate is the
+// rank of its fused form.  Complete-pivoting elimination with a relative
+// threshold well above rounding and well below any physical singular value.
+int operator_schmidt_rank(const double *m) {
+    cd a[4][4];
+    for (int a0p = 0; a0p < 2; ++a0p)
+        for (int b0p = 0; b0p < 2; ++b0p)
+            for (int a0 = 0; a0 < 2; ++a0)
+                for (int b0 = 0; b0 < 2; ++b0) {
+                    int r = a0p * 2 + b0p, c = a0 * 2 + b0;   // O[(a' b'), (a b)]
+                    int i = r * 4 + c;
+                    a[a0p * 2 + a0][b0p * 2 + b0] = cd(m[2 * i], m[2 * i + 1]);
+                }
+    double scale = 0;
+    for (auto &row : a)
+        for (auto &x : row) scale = std::max(scale, std::abs(x));
+    if (scale == 0) return 0;
+    int rank = 0;
+    bool rused[4] = {}, cused[4] = {};
+    for (int step = 0; step < 4; ++step) {
+        int pr = -1, pc = -1;
+        double best = 0;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c)
+                if (!rused[r] && !cused[c] && std::abs(a[r][c]) > best) {
+                    best = std::abs(a[r][c]);
+                    pr = r;
+                    pc = c;
+                }
+        if (pr < 0 || best <= 1e-10 * scale) break;
+        ++rank;
+        rused[pr] = cused[pc] = true;
+        for (int r = 0; r < 4; ++r) {
+            if (rused[r]) continue;
+            cd f = a[r][pc] / a[pr][pc];
+            for (int c = 0; c < 4; ++c) a[r][c] -= f * a[pr][c];
+        }
+    }
+    return rank;
+}
+
+// ----------------------------------------------------------------------------
+// path search (supplement: score, Cost, Algorithm 1)
+
+namespace {
+
+struct QMask {
+    uint64_t w[2] = {0, 0};
+    void set(int q) { w[q >> 6] |= 1ULL << (q & 63); }
+    bool has(int q) const { return (w[q >> 6] >> (q & 63)) & 1ULL; }
+    bool operator==(const QMask &o) const { return w[0] == o.w[0] && w[1] == o.w[1]; }
+};
+struct QMaskHash {
+    size_t operator()(const QMask &m) const {
+        uint64_t h = m.w[0] * 0x9E3779B97F4A7C15ULL ^ (m.w[1] + 0x632BE59BD9B4E019ULL + (m.w[0] << 6));
+        return (size_t)(h ^ (h >> 29));
+    }
+};
+
+// Graph restricted to bonds of dimension > 1 (a bond of dimension 1 neither
+// costs anything nor connects anything).
+struct PG {
+    int n = 0;
+    std::vector<std::pair<int, int>> edges;
+    std::vector<double> d;
+    std::vector<std::vector<int>> legs;   // per node: filtered edge ids
+    std::vector<std::vector<int>> nbr;    // per node: neighbours
+};
+
+PG make_pg(int n, const std::vector<std::pair<int, int>> &edges, const std::vector<double> &dims) {
+    PG g;
+    g.n = n;
+    g.legs.assign(n, {});
+    g.nbr.assign(n, {});
+    for (size_t e = 0; e < edges.size(); ++e) {
+        if (!(dims[e] > 1.0)) continue;
+        int id = (int)g.edges.size();
+        g.edges.push_back(edges[e]);
+        g.d.push_back(dims[e]);
+        g.legs[edges[e].first].push_back(id);
+        g.legs[edges[e].second].push_back(id);
+        g.nbr[edges[e].first].push_back(edges[e].second);
+        g.nbr[edges[e].second].push_back(edges[e].first);
+    }
+    for (auto &v : g.nbr) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    return g;
+}
+
+// Score of a fixed order: sum of Cost(C^{set}, C^{j}) with Cost the product
+// of the dimensions of every bond carried by either tensor.
+double order_score(const PG &g, const std::vector<int> &order, double *peak, int *max_rank) {
+    std::vector<char> in(g.n, 0), open(g.edges.size(), 0);
+    double size = 1, score = 0, pk = 0;
+    int rank = 0, mr = 0;
+    for (size_t m = 0; m < order.size(); ++m) {
+        int j = order[m];
+        double K = 1, N = 1;
+        int shared = 0, fresh = 0;
+        for (int e : g.legs[j]) {
+            int other = g.edges[e].first == j ? g.edges[e].second : g.edges[e].first;
+            if (in[other]) { K *= g.d[e]; ++shared; } else { N *= g.d[e]; ++fresh; }
+        }
+        if (m > 0) score += size * N;
+        size = (m == 0) ? N : size / K * N;
+        rank = (m == 0) ? fresh : rank - shared + fresh;
+        in[j] = 1;
+        pk = std::max(pk, size);
+        mr = std::max(mr, rank);
+    }
+    if (peak) *peak = pk;
+    if (max_rank) *max_rank = mr;
+    return score;
+}
+
+// Greedy linear path: from every start, repeatedly absorb the neighbouring
+// tensor with the least step cost (criterion 0) or the least resulting size
+// (criterion 1); the best full path over both criteria and all starts wins.
+PathResult greedy(const PG &g) {
+    PathResult best;
+    best.score = std::numeric_limits<double>::infinity();
+    const int n = g.n;
+    for (int crit = 0; crit < 2; ++crit)
+    for (int start = 0; start < n; ++start) {
+        std::vector<char> in(n, 0);
+        std::vector<int> adj(n, 0), order{start};
+        in[start] = 1;
+        double size = 1, score = 0, peak = 0;
+        int rank = 0, mr = 0;
+        for (int e : g.legs[start]) { size *= g.d[e]; ++rank; }
+        peak = size;
+        mr = rank;
+        for (int x : g.nbr[start]) adj[x]++;
+        for (int m = 1; m < n; ++m) {
+            bool any_adj = false;
+            for (int j = 0; j < n; ++j)
+                if (!in[j] && adj[j]) { any_adj = true; break; }
+            int bj = -1, bshared = 0, bfresh = 0;
+            double bcost = 0, bsize = 0;
+            for (int j = 0; j < n; ++j) {
+                if (in[j] || (any_adj && !adj[j])) continue;
+                double K = 1, N = 1;
+                int shared = 0, fresh = 0;
+                for (int e : g.legs[j]) {
+                    int other = g.edges[e].first == j ? g.edges[e].second : g.edges[e].first;
+                    if (in[other]) { K *= g.d[e]; ++shared; } else { N *= g.d[e]; ++fresh; }
+                }
+                double cost = size * N, ns = size / K * N;
+                bool better = crit == 0 ? (cost < bcost || (cost == bcost && ns < bsize))
+                                        : (ns < bsize || (ns == bsize && cost < bcost));
+                if (bj < 0 || better) {
+                    bj = j; bcost = cost; bsize = ns; bshared = shared; bfresh = fresh;
+                }
+            }
+            in[bj] = 1;
+            order.push_back(bj);
+            for (int x : g.nbr[bj]) adj[x]++;
+            score += bcost;
+            size = bsize;
+            rank += bfresh - bshared;
+            peak = std::max(peak, size);
+            mr = std::max(mr, rank);
+            if (score > best.score) break;
+        }
+        if ((int)order.size() == n &&
+            (score < best.score || (score == best.score && peak < best.peak))) {
+            best.order = order;
+            best.score = score;
+            best.peak = peak;
+            best.max_rank = mr;
+        }
+    }
+    best.states = n;
+    best.complete = true;
+    return best;
+}
+
+struct Node {
+    QMask set;
+    double score;
+    int32_t parent;
+    int16_t q, c, m, pad;
+};
+
+struct QItem {
+    double score;
+    int32_t m;
+    int64_t seq;
+    int32_t node;
+};
+struct QCmp {
+    // std::priority_queue pops the "largest": order so that the least score,
+    // then the longest path, then the earliest push comes out first.
+    bool operator()(const QItem &a, const QItem &b) const {
+        if (a.score != b.score) return a.score > b.score;
+        if (a.m != b.m) return a.m < b.m;
+        return a.seq > b.seq;
+    }
+};
+
+// Algorithm 1 of the supplement: best-first search over partial paths, keyed
+// by the set of absorbed qubits, with the three assumptions restricting the
+// start (boundary qubits), the rank of intermediates (<= M) and connectivity
+// (connected, or connected plus one isolated qubit that the next step joins).
+PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_states,
+                      double upper, const PathResult *fallback) {
+    const int n = g.n;
+    std::vector<Node> arena;
+    arena.reserve(1 << 16);
+    std::priority_queue<QItem, std::vector<QItem>, QCmp> pq;
+    std::unordered_set<QMask, QMaskHash> visited;
+    int64_t seq = 0;
+
+    int maxdeg = 0;
+    for (int v = 0; v < n; ++v) maxdeg = std::max<int>(maxdeg, (int)g.nbr[v].size());
+    for (int v = 0; v < n; ++v) {
+        bool boundary = !assumptions || (int)g.nbr[v].size() < maxdeg;
+        if (!boundary) continue;
+        Node nd;
+        nd.set.set(v);
+        nd.score = 0;
+        nd.parent = -1;
+        nd.q = (int16_t)v;
+        nd.c = -1;
+        nd.m = 1;
+        arena.push_back(nd);
+        pq.push({0.0, 1, seq++, (int32_t)arena.size() - 1});
+    }
+    PathResult res;
+    std::vector<char> in(n), open(g.edges.size()), adj(n), near(n);
+    while (!pq.empty()) {
+        QItem it = pq.top();
+        pq.pop();
+        const Node cur = arena[it.node];
+        if (visited.count(cur.set)) continue;
+        visited.insert(cur.set);
+        res.states++;
+        if (cur.m == n) {
+            std::vector<int> order;
+            for (int i = it.node; i >= 0; i = arena[i].parent) order.push_back(arena[i].q);
+            std::reverse(order.begin(), order.end());
+            res.order = order;
+            res.score = cur.score;
+            order_score(g, order, &res.peak, &res.max_rank);
+            res.complete = true;
+            return res;
+        }
+        if (max_states > 0 && res.states >= max_states) break;
+        for (int v = 0; v < n; ++v) in[v] = cur.set.has(v);
+        double size = 1;
+        int rank = 0;
+        for (size_t e = 0; e < g.edges.size(); ++e) {
+            open[e] = in[g.edges[e].first] != in[g.edges[e].second];
+            if (open[e]) { size *= g.d[e]; ++rank; }
+        }
+        // candidate generation
+        std::fill(adj.begin(), adj.end(), 0);
+        for (int v = 0; v < n; ++v)
+            if (in[v])
+                for (int x : g.nbr[v])
+                    if (!in[x]) adj[x] = 1;
+        auto consider = [&](int j) {
+            double K = 1, N = 1;
+            int shared = 0, fresh = 0;
+            for (int e : g.legs[j]) {
+                if (open[e]) { K *= g.d[e]; ++shared; } else { N *= g.d[e]; ++fresh; }
+            }
+            int nrank = rank - shared + fresh;
+            if (assumptions && nrank > max_rank) return;
+            double ns = cur.score + size * N;
+            if (ns > upper) return;
+            Node nd;
+            nd.set = cur.set;
+            nd.set.set(j);
+            if (visited.count(nd.set)) return;
+            nd.score = ns;
+            nd.parent = it.node;
+            nd.q = (int16_t)j;
+            nd.c = (int16_t)(shared > 0 ? -1 : j);   // conn(): -1 when joined to the set
+            nd.m = (int16_t)(cur.m + 1);
+            arena.push_back(nd);
+            pq.push({ns, nd.m, seq++, (int32_t)arena.size() - 1});
+        };
+        if (!assumptions) {
+            for (int j = 0; j < n; ++j)
+                if (!in[j]) consider(j);
+        } else if (cur.c < 0) {
+            std::fill(near.begin(), near.end(), 0);
+            for (int j = 0; j < n; ++j)
+                if (adj[j]) {
+                    consider(j);
+                    for (int x : g.nbr[j])
+                        if (!in[x] && !adj[x]) near[x] = 1;
+                }
+            for (int j = 0; j < n; ++j)
+                if (near[j]) consider(j);      // the single isolated qubit (assumption 3)
+        } else {
+            const int iso = cur.c;
+            for (int j = 0; j < n; ++j) {
+                if (!adj[j]) continue;
+                bool to_iso = false, to_main = false;
+                for (int x : g.nbr[j]) {
+                    if (x == iso) to_iso = true;
+                    else if (in[x]) to_main = true;
+                }
+                if (to_iso && to_main) consider(j);
+            }
+        }
+    }
+    // budget exhausted or no admissible path below the bound: keep the fallback
+    if (fallback) {
+        PathResult f = *fallback;
+        f.states = res.states;
+        f.complete = pq.empty();   // empty queue: nothing admissible beats the fallback
+        return f;
+    }
+    fail(TNS_E_BAD_PATH, "path search found no admissible path");
+}
+
+}  // namespace
+
+PathResult path_search(int n, const std::vector<std::pair<int, int>> &edges,
+                       const std::vector<double> &dims, int mode, int max_rank,
+                       bool assumptions, int64_t max_states) {
+    PG g = make_pg(n, edges, dims);
+    PathResult gr = greedy(g);
+    if (mode == TNS_PATH_GREEDY) return gr;
+    if (mode != TNS_PATH_ALGORITHM1) fail(TNS_E_INVALID_ARG, "unknown path mode");
+    int M = max_rank > 0 ? max_rank : gr.max_rank;
+    double upper = assumptions ? gr.score : std::numeric_limits<double>::infinity();
+    PathResult r = algorithm1(g, M, assumptions, max_states > 0 ? max_states : 4000000, upper,
+                              assumptions ? &gr : nullptr);
+    r.max_rank = std::max(r.max_rank, 0);
+    // report the rank bound actually used by the search
+    if (assumptions) r.max_rank = M;
+    return r;
+}
+
+double path_score(int n, const std::vector<std::pair<int, int>> &edges,
+                  const std::vector<double> &dims, const std::vector<int> &order, double *peak,
+                  int *max_rank) {
+    PG g = make_pg(n, edges, dims);
+    return order_score(g, order, peak, max_rank);
+}
+
+// ----------------------------------------------------------------------------
+// fusion of single-qubit gates into two-qubit gates ("Single-qubit gates are
+// absorbed", gate-operation paragraph) and the two-sided split
+
+namespace {
+
+int make_chain(Plan &p, std::vector<int> &pending) {
+    if (pending.empty()) return -1;
+    int id = (int)p.chain_off.size();
+    p.chain_off.push_back((int32_t)p.chain_flat.size());
+    p.chain_len.push_back((int32_t)pending.size());
+    for (int gi : pending) p.chain_flat.push_back(gi);
+    pending.clear();
+    return id;
+}
+
+// Fuse one side's gates (given in time order).  Returns the fused ops in time
+// order (indices into p.fuse).  Leftover single-qubit gates go to the
+// boundary chains: on the ket side into the last two-qubit gate on that qubit
+// (or the initial product state if there is none), on the bra side into the
+// final product state <s|.
+std::vector<int> fuse_side(Plan &p, const std::vector<int> &gids, bool bra) {
+    const Circuit &c = p.circ;
+    std::vector<std::vector<int>> pending(c.n);
+    std::vector<int> last(c.n, -1), out;
+    for (int gi : gids) {
+        const tns_gate &g = c.gates[gi];
+        if (g.q1 < 0) {
+            pending[g.q0].push_back(gi);
+            continue;
+        }
+        FuseDesc f{};
+        f.gate = gi;
+        f.pre0 = make_chain(p, pending[g.q0]);
+        f.pre1 = make_chain(p, pending[g.q1]);
+        f.post0 = f.post1 = -1;
+        f.transpose = bra ? 1 : 0;
+        f.chi = operator_schmidt_rank(g.m);
+        out.push_back((int)p.fuse.size());
+        p.fuse.push_back(f);
+        last[g.q0] = last[g.q1] = out.back();
+    }
+    for (int q = 0; q < c.n; ++q) {
+        if (pending[q].empty()) continue;
+        if (!bra && last[q] >= 0) {
+            FuseDesc &f = p.fuse[last[q]];
+            int ch = make_chain(p, pending[q]);
+            if (c.gates[f.gate].q0 == q) f.post0 = ch; else f.post1 = ch;
+        } else {
+            int ch = make_chain(p, pending[q]);
+            (bra ? p.bra_final_chain : p.ket_init_chain)[q] = ch;
+        }
+    }
+    return out;
+}
+
+int64_t shape_elems(const SiteShape &s) {
+    int64_t v = 1;
+    for (int i = 0; i < s.n; ++i) v *= s.d[i];
+    return v;
+}
+
+// Bond-dimension bookkeeping of one side (Eqs. (3)-(6)).  A gate widens its
+// bond by chi; the SVD of Eq. (5) can then keep at most min(rows, cols)
+// singular values, rows = 2 * (product of the site's other bonds).  The
+// smaller of the two sites' row counts bounds the kept rank; when it is
+// below the widened bond the compression is planned on that site.  Exact
+// zeros among the kept singular values (non-generic circuits) are kept as
+// padding, so every bitstring shares one shape.
+SideEvolution evolve_side(const Plan &p, const std::vector<int> &fused_ids, bool reverse) {
+    const Circuit &c = p.circ;
+    SideEvolution s;
+    std::vector<int> dim(c.g.edges.size(), 1);
+    auto shape = [&](int q) {
+        SiteShape sh{};
+        sh.n = 1 + (int)c.g.legs[q].size();
+        sh.d[0] = 2;
+        for (size_t i = 0; i < c.g.legs[q].size(); ++i) sh.d[1 + i] = dim[c.g.legs[q][i]];
+        return sh;
+    };
+    s.cap.assign(c.n, 2);
+    std::vector<int> order = fused_ids;
+    if (reverse) std::reverse(order.begin(), order.end());
+    for (int fid : order) {
+        const FuseDesc &f = p.fuse[fid];
+        const tns_gate &g = c.gates[f.gate];
+        EvoOp op{};
+        op.fused = fid;
+        op.q0 = g.q0;
+        op.q1 = g.q1;
+        op.edge = c.g.edge_id(g.q0, g.q1);
+        op.chi = f.chi;
+        op.leg0 = c.g.leg_of(g.q0, op.edge);
+        op.leg1 = c.g.leg_of(g.q1, op.edge);
+        op.s0 = shape(g.q0);
+        op.s1 = shape(g.q1);
+        op.d_before = dim[op.edge];
+        dim[op.edge] *= f.chi;
+        op.d_grown = dim[op.edge];
+        SiteShape g0 = shape(g.q0), g1 = shape(g.q1);
+        s.cap[g.q0] = std::max(s.cap[g.q0], shape_elems(g0));
+        s.cap[g.q1] = std::max(s.cap[g.q1], shape_elems(g1));
+        int64_t r0 = shape_elems(g0) / op.d_grown, r1 = shape_elems(g1) / op.d_grown;
+        int64_t r = std::min(r0, r1);
+        if (r < op.d_grown) {
+            op.comp = (r0 < r1 || (r0 == r1 && g.q0 < g.q1)) ? 0 : 1;
+            dim[op.edge] = (int)r;
+        } else {
+            op.comp = -1;
+        }
+        op.d_after = dim[op.edge];
+        s.ops.push_back(op);
+    }
+    s.bond = dim;
+    for (int q = 0; q < c.n; ++q) s.final_shape.push_back(shape(q));
+    return s;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// step compilation
+
+namespace {
+
+// Merge adjacent axes that stay adjacent (stride[a] == stride[a+1]*size[a+1])
+// and drop unit axes.
+Gather compact(const std::vector<int64_t> &size, const std::vector<int64_t> &stride) {
+    std::vector<int64_t> sz, st;
+    for (size_t a = 0; a < size.size(); ++a) {
+        if (size[a] == 1) continue;
+        if (!sz.empty() && st.back() == stride[a] * size[a]) {
+            sz.back() *= size[a];
+            st.back() = stride[a];
+        } else {
+            sz.push_back(size[a]);
+            st.push_back(stride[a]);
+        }
+    }
+    if (sz.empty()) { sz.push_back(1); st.push_back(0); }
+    if ((int)sz.size() > kMaxGatherDims)
+        fail(TNS_E_UNSUPPORTED, "tensor has more than " + std::to_string(kMaxGatherDims) +
+                                    " non-mergeable axes");
+    Gather g{};
+    g.n = (int)sz.size();
+    for (int a = 0; a < g.n; ++a) { g.size[a] = sz[a]; g.stride[a] = st[a]; }
+    return g;
+}
+
+}  // namespace
+
+static void compile_steps(Plan &p) {
+    const Circuit &c = p.circ;
+    const int n = c.n;
+    const auto &order = p.path.order;
+    std::vector<int64_t> d(c.g.edges.size());
+    std::vector<char> is_cut(c.g.edges.size(), 0);
+    for (int e : p.cuts) is_cut[e] = 1;
+    for (size_t e = 0; e < d.size(); ++e) d[e] = is_cut[e] ? 1 : p.bond_overlap[e];
+    std::vector<int> pos(n);
+    for (int m = 0; m < n; ++m) pos[order[m]] = m;
+    auto consumed = [&](int e) { return std::max(pos[c.g.edges[e].first], pos[c.g.edges[e].second]); };
+    auto logical_legs = [&](int q) {
+        std::vector<int> v;
+        for (int e : c.g.legs[q])
+            if (d[e] > 1) v.push_back(e);
+        return v;
+    };
+    // physical stride of bond e inside site q's overlap tensor (bonds in edge-id order)
+    auto site_stride = [&](int q, int e) {
+        int64_t st = 1;
+        for (int i = (int)c.g.legs[q].size() - 1; i >= 0; --i) {
+            if (c.g.legs[q][i] == e) return st;
+            st *= p.site_dims[q][i];
+        }
+        fail(TNS_E_BAD_PATH, "internal: bond not on site");
+    };
+    auto by_consumption_desc = [&](std::vector<int> &v) {
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+            int ca = consumed(a), cb = consumed(b);
+            return ca != cb ? ca > cb : a < b;
+        });
+    };
+    auto prod = [&](const std::vector<int> &v) {
+        int64_t x = 1;
+        for (int e : v) x *= d[e];
+        return x;
+    };
+
+    p.steps.clear();
+    const int elem = (p.precision == TNS_C128) ? 16 : 8;
+    p.peak_elems = 0;
+    p.max_b_elems = 0;
+    p.flops_per_amp = p.gemm_bytes_per_amp = p.permute_bytes_per_amp = 0;
+    p.path_score = 0;
+
+    // step 0: the starting tensor
+    Step s0;
+    s0.site = order[0];
+    s0.n_legs = logical_legs(order[0]);
+    by_consumption_desc(s0.n_legs);
+    {
+        std::vector<int64_t> sz, st;
+        for (int e : s0.n_legs) { sz.push_back(d[e]); st.push_back(site_stride(order[0], e)); }
+        s0.bgather = compact(sz, st);
+    }
+    s0.N = prod(s0.n_legs);
+    s0.out_elems = s0.N;
+    p.peak_elems = s0.N;
+    std::vector<int> T = s0.n_legs;
+    p.steps.push_back(s0);
+
+    for (int m = 1; m < n; ++m) {
+        const int j = order[m];
+        Step s;
+        s.site = j;
+        s.t_legs = T;
+        std::vector<int> lj = logical_legs(j);
+        std::vector<int> S, Mv;
+        for (int e : T)
+            if (std::find(lj.begin(), lj.end(), e) != lj.end()) S.push_back(e); else Mv.push_back(e);
+        // Are the shared legs already the trailing legs of T?
+        bool trailing = true;
+        for (size_t i = 0; i < S.size(); ++i)
+            if (T[T.size() - S.size() + i] != S[i]) trailing = false;
+        if (!trailing) {
+            s.permute = true;
+            by_consumption_desc(Mv);
+            std::vector<int> neworder = Mv;
+            neworder.insert(neworder.end(), S.begin(), S.end());
+            // source strides of T (row-major over T)
+            std::vector<int64_t> tstride(T.size());
+            int64_t st = 1;
+            for (int i = (int)T.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[T[i]]; }
+            std::vector<int64_t> sz, sst;
+            for (int e : neworder) {
+                int i = (int)(std::find(T.begin(), T.end(), e) - T.begin());
+                sz.push_back(d[e]);
+                sst.push_back(tstride[i]);
+            }
+            s.perm = compact(sz, sst);
+            p.permute_bytes_per_amp += 2.0 * elem * (double)prod(T);
+        }
+        s.m_legs = Mv;
+        s.k_legs = S;
+        for (int e : lj)
+            if (std::find(S.begin(), S.end(), e) == S.end()) s.n_legs.push_back(e);
+        by_consumption_desc(s.n_legs);
+        s.M = prod(Mv);
+        s.K = prod(S);
+        s.N = prod(s.n_legs);
+        {
+            // B[n][k]: new legs (slow) then shared legs in T's order (fast)
+            std::vector<int64_t> sz, st;
+            for (int e : s.n_legs) { sz.push_back(d[e]); st.push_back(site_stride(j, e)); }
+            for (int e : S) { sz.push_back(d[e]); st.push_back(site_stride(j, e)); }
+            s.bgather = compact(sz, st);
+        }
+        s.out_elems = s.M * s.N;
+        const bool last = (m == n - 1);
+        if (last) {
+            if (s.M != 1 || s.N != 1) fail(TNS_E_BAD_PATH, "internal: final step is not a scalar");
+            s.kernel = 2;
+        } else if (s.K >= 16 && s.N >= 16 && s.M >= 16 && s.K % 2 == 0) {
+            s.kernel = 0;
+        } else {
+            s.kernel = 1;
+        }
+        T = Mv;
+        T.insert(T.end(), s.n_legs.begin(), s.n_legs.end());
+        p.peak_elems = std::max(p.peak_elems, std::max(s.out_elems, s.M * s.K));
+        p.max_b_elems = std::max(p.max_b_elems, s.K * s.N);
+        const double mkn = (double)s.M * (double)s.K * (double)s.N;
+        p.path_score += mkn;
+        p.flops_per_amp += 8.0 * mkn;
+        p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
+        p.steps.push_back(s);
+    }
+    const double ns = (double)p.n_slices;
+    p.flops_per_amp *= ns;
+    p.gemm_bytes_per_amp *= ns;
+    p.permute_bytes_per_amp *= ns;
+
+    // per-site slice maps (slice index = mixed radix over the cuts, last fastest)
+    p.slice_map.assign(n, SliceMap{});
+    if ((int)p.cuts.size() > kMaxCuts) fail(TNS_E_UNSUPPORTED, "too many cut bonds");
+    int64_t div = 1;
+    for (int ci = (int)p.cuts.size() - 1; ci >= 0; --ci) {
+        const int e = p.cuts[ci];
+        for (int q : {c.g.edges[e].first, c.g.edges[e].second}) {
+            SliceMap &sm = p.slice_map[q];
+            sm.div[sm.n] = div;
+            sm.dim[sm.n] = p.bond_overlap[e];
+            sm.stride[sm.n] = site_stride(q, e);
+            sm.n++;
+        }
+        div *= p.bond_overlap[e];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// whole host plan
+
+static void split_groups(const Circuit &c, int k, std::vector<int> &ket, std::vector<int> &bra) {
+    ket.clear();
+    bra.clear();
+    for (int i = 0; i < (int)c.gates.size(); ++i) (c.gates[i].cycle < k ? ket : bra).push_back(i);
+}
+
+static void evolve_both(Plan &p, int k) {
+    p.fuse.clear();
+    p.chain_flat.clear();
+    p.chain_off.clear();
+    p.chain_len.clear();
+    p.ket_init_chain.assign(p.circ.n, -1);
+    p.bra_final_chain.assign(p.circ.n, -1);
+    std::vector<int> kg, bg;
+    split_groups(p.circ, k, kg, bg);
+    std::vector<int> kf = fuse_side(p, kg, false);
+    std::vector<int> bf = fuse_side(p, bg, true);
+    p.n_fused_ket = (int)kf.size();
+    p.n_fused_bra = (int)bf.size();
+    p.ket = evolve_side(p, kf, false);
+    p.bra = evolve_side(p, bf, true);
+    const auto &E = p.circ.g.edges;
+    p.bond_overlap.assign(E.size(), 1);
+    for (size_t e = 0; e < E.size(); ++e) p.bond_overlap[e] = p.ket.bond[e] * p.bra.bond[e];
+}
+
+static std::vector<double> dims_with_cuts(const Plan &p, const std::vector<int> &cuts) {
+    std::vector<double> d(p.bond_overlap.begin(), p.bond_overlap.end());
+    for (int e : cuts) d[e] = 1;
+    return d;
+}
+
+// Sizes of the intermediates along a fixed order; returns the step index of
+// the largest one and fills its open bonds.
+static double largest_intermediate(const Circuit &c, const std::vector<double> &d,
+                                   const std::vector<int> &order, std::vector<int> *open_out) {
+    const auto &E = c.g.edges;
+    std::vector<char> in(c.n, 0);
+    double best = -1;
+    for (int j : order) {
+        in[j] = 1;
+        double sz = 1;
+        for (size_t e = 0; e < E.size(); ++e)
+            if (d[e] > 1 && in[E[e].first] != in[E[e].second]) sz *= d[e];
+        if (sz > best) {
+            best = sz;
+            if (open_out) {
+                open_out->clear();
+                for (size_t e = 0; e < E.size(); ++e)
+                    if (d[e] > 1 && in[E[e].first] != in[E[e].second]) open_out->push_back((int)e);
+            }
+        }
+    }
+    return best;
+}
+
+struct Sliced {
+    std::vector<int> cuts;
+    double total = 0;   // slices x score
+    double peak = 0;
+    double slices = 1;
+};
+
+// Cuts for a fixed contraction order (overlap paragraph: a cut bond of
+// dimension D splits the network into D sub-networks with the bond removed).
+// For a fixed order the sliced cost is exact: D x score with the bond at
+// dimension 1.  While the largest intermediate exceeds the limit, cut the open
+// bond of that intermediate that minimises the total.
+static Sliced cuts_for_order(const Plan &p, const std::vector<int> &order, std::vector<int> cuts,
+                             double limit) {
+    const Circuit &c = p.circ;
+    Sliced r;
+    for (int it = 0; it < 4 * kMaxCuts; ++it) {
+        std::vector<double> d = dims_with_cuts(p, cuts);
+        std::vector<int> open;
+        double pk = largest_intermediate(c, d, order, &open);
+        if (pk <= limit) break;
+        int be = -1;
+        double bt = 0, bp = 0;
+        for (int e : open) {
+            std::vector<double> dt = d;
+            dt[e] = 1;
+            double pke = 0;
+            double t = path_score(c.n, c.g.edges, dt, order, &pke, nullptr) * d[e];
+            if (be < 0 || t < bt || (t == bt && pke < bp)) { be = e; bt = t; bp = pke; }
+        }
+        if (be < 0) break;
+        cuts.push_back(be);
+    }
+    std::vector<double> d = dims_with_cuts(p, cuts);
+    r.cuts = cuts;
+    r.slices = 1;
+    for (int e : cuts) r.slices *= p.bond_overlap[e];
+    r.total = path_score(c.n, c.g.edges, d, order, &r.peak, nullptr) * r.slices;
+    return r;
+}
+
+// Cut choice ("chosen empirically ... where the lattice is the thinnest") is
+// automated: plan a path on the whole network, cut against that path, then
+// also re-plan the path on the sliced network as the paper does for its
+// sub-networks, and keep whichever has the least total cost within the limit.
+static void choose_cuts_and_path(Plan &p) {
+    const Circuit &c = p.circ;
+    const auto &E = c.g.edges;
+    const double limit = (double)(p.opts.max_intermediate_elems ? p.opts.max_intermediate_elems
+                                                                 : (1ULL << 32));
+    p.cuts.clear();
+    std::vector<int> given;
+    if (p.opts.n_cuts >= 0) {
+        for (int i = 0; i < p.opts.n_cuts; ++i) {
+            int e = p.opts.cut_edges[i];
+            if (e < 0 || e >= (int)E.size() || std::count(given.begin(), given.end(), e))
+                fail(TNS_E_BAD_PATH, "bad cut edge " + std::to_string(e));
+            given.push_back(e);
+        }
+    }
+    auto search = [&](const std::vector<double> &d, int mode) {
+        return path_search(c.n, E, d, mode, p.opts.max_rank, p.opts.path_assumptions != 0,
+                           p.opts.max_search_states);
+    };
+    if (p.opts.path) {
+        PathResult r;
+        r.order.assign(p.opts.path, p.opts.path + c.n);
+        Sliced s = p.opts.n_cuts >= 0 ? cuts_for_order(p, r.order, given, 1e300)
+                                      : cuts_for_order(p, r.order, {}, limit);
+        p.cuts = s.cuts;
+        r.score = path_score(c.n, E, dims_with_cuts(p, p.cuts), r.order, &r.peak, &r.max_rank);
+        p.path = r;
+    } else if (p.opts.n_cuts >= 0) {
+        p.cuts = given;
+        p.path = search(dims_with_cuts(p, p.cuts), p.opts.path_mode);
+    } else {
+        std::vector<double> d0 = dims_with_cuts(p, {});
+        PathResult best_path;
+        Sliced best;
+        best.total = std::numeric_limits<double>::infinity();
+        auto consider = [&](const PathResult &r, const Sliced &s) {
+            if (s.peak <= limit && s.total < best.total) { best = s; best_path = r; }
+        };
+        std::vector<int> modes{TNS_PATH_GREEDY};
+        if (p.opts.path_mode != TNS_PATH_GREEDY) modes.push_back(p.opts.path_mode);
+        for (int mode : modes) {
+            PathResult r = search(d0, mode);
+            Sliced s = cuts_for_order(p, r.order, {}, limit);
+            consider(r, s);
+            if (s.cuts.empty()) continue;
+            // re-plan on the sliced network (the paper's order of operations)
+            std::vector<double> ds = dims_with_cuts(p, s.cuts);
+            PathResult r2 = search(ds, mode);
+            Sliced s2 = cuts_for_order(p, r2.order, s.cuts, limit);
+            consider(r2, s2);
+        }
+        if (!std::isfinite(best.total))
+            fail(TNS_E_OUT_OF_MEMORY, "no cut set brings the largest intermediate under the limit");
+        p.cuts = best.cuts;
+        p.path = best_path;
+        p.path.score = path_score(c.n, E, dims_with_cuts(p, p.cuts), p.path.order, &p.path.peak, nullptr);
+    }
+    if ((int)p.path.order.size() != c.n) fail(TNS_E_BAD_PATH, "path search returned no full path");
+    if ((int)p.cuts.size() > kMaxCuts) fail(TNS_E_UNSUPPORTED, "too many cut bonds");
+    p.n_slices = 1;
+    for (int e : p.cuts) {
+        if (p.n_slices > ((int64_t)1 << 40) / p.bond_overlap[e]) fail(TNS_E_OUT_OF_MEMORY, "too many slices");
+        p.n_slices *= p.bond_overlap[e];
+    }
+}
+
+void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
+    p.circ = c;
+    p.opts = opts;
+    p.precision = opts.precision;
+    if (opts.precision < TNS_C128 || opts.precision > TNS_C64_SPLIT_BF16_6)
+        fail(TNS_E_INVALID_ARG, "unknown precision");
+    if (opts.precision >= TNS_C64_SPLIT_BF16_3)
+        fail(TNS_E_UNSUPPORTED, "split-bf16 contraction is not available in this build");
+    if (opts.n_open != 0 || opts.open_qubits) fail(TNS_E_UNSUPPORTED, "open qubits are reserved");
+    if (opts.path) {
+        std::vector<char> seen(c.n, 0);
+        for (int i = 0; i < c.n; ++i) {
+            int q = opts.path[i];
+            if (q < 0 || q >= c.n || seen[q]) fail(TNS_E_BAD_PATH, "path is not a permutation of 0..N-1");
+            seen[q] = 1;
+        }
+    }
+    if (opts.n_cuts > 0 && !opts.cut_edges) fail(TNS_E_INVALID_ARG, "n_cuts > 0 with NULL cut_edges");
+    const int depth = c.max_cycle + 1;
+    if (opts.split_cycle >= 0) {
+        p.split = opts.split_cycle;
+    } else {
+        // choose the split with the least sliced cost of a greedy path
+        const double limit = (double)(opts.max_intermediate_elems ? opts.max_intermediate_elems
+                                                                   : (1ULL << 32));
+        double best = std::numeric_limits<double>::infinity();
+        int bk = 0;
+        for (int k = 0; k <= depth; ++k) {
+            evolve_both(p, k);
+            std::vector<double> d(p.bond_overlap.begin(), p.bond_overlap.end());
+            PathResult r = path_search(c.n, c.g.edges, d, TNS_PATH_GREEDY, 0, true, 0);
+            Sliced sl = cuts_for_order(p, r.order, {}, limit);
+            double t = sl.peak <= limit ? sl.total : std::numeric_limits<double>::infinity();
+            if (t < best) { best = t; bk = k; }
+        }
+        p.split = bk;
+    }
+    evolve_both(p, p.split);
+    // overlap site tensors (Eq. (8)): bond dims multiply
+    p.site_dims.assign(c.n, {});
+    p.site_elems.assign(c.n, 1);
+    for (int q = 0; q < c.n; ++q)
+        for (int e : c.g.legs[q]) {
+            p.site_dims[q].push_back(p.bond_overlap[e]);
+            p.site_elems[q] *= p.bond_overlap[e];
+        }
+    choose_cuts_and_path(p);
+    compile_steps(p);
+
+    // scratch for the SVD's V' of the bra side (per bitstring)
+    p.bra_scratch_elems = 1;
+    for (const EvoOp &op : p.bra.ops)
+        if (op.comp >= 0) {
+            int64_t rows = 1;
+            const SiteShape &s = op.comp == 0 ? op.s0 : op.s1;
+            for (int i = 0; i < s.n; ++i) rows *= s.d[i];
+            rows = rows / op.d_before;   // rows of the widened tensor: 2 * other bonds
+            p.bra_scratch_elems = std::max<int64_t>(p.bra_scratch_elems, rows * op.d_grown);
+        }
+    for (const EvoOp &op : p.ket.ops)
+        if (op.comp >= 0) {
+            int64_t rows = 1;
+            const SiteShape &s = op.comp == 0 ? op.s0 : op.s1;
+            for (int i = 0; i < s.n; ++i) rows *= s.d[i];
+            rows = rows / op.d_before;
+            p.bra_scratch_elems = std::max<int64_t>(p.bra_scratch_elems, rows * op.d_grown);
+        }
+
+    // reporting: Eq. (9) with the Sycamore error rates quoted in the paper
+    int n1 = 0, n2 = 0;
+    for (const auto &g : c.gates) (g.q1 < 0 ? n1 : n2)++;
+    double f = std::pow(1 - 0.0016, n1) * std::pow(1 - 0.0062, n2) * std::pow(1 - 0.038, c.n);
+    p.fidelity = f;
+    p.n_samples = (3.0 / f) * (3.0 / f);
+
+    p.info_path = p.path.order;
+    p.info_m.clear(); p.info_k.clear(); p.info_n.clear(); p.info_kernel.clear(); p.info_permute.clear();
+    for (size_t i = 1; i < p.steps.size(); ++i) {
+        p.info_m.push_back(p.steps[i].M);
+        p.info_k.push_back(p.steps[i].K);
+        p.info_n.push_back(p.steps[i].N);
+        p.info_kernel.push_back(p.steps[i].kernel);
+        p.info_permute.push_back(p.steps[i].permute ? 1 : 0);
+    }
+    const int elem = p.precision == TNS_C128 ? 16 : 8;
+    // one unit: two boundary buffers, the B operand (embedded form is 2x) and the partial
+    p.unit_stride = (p.peak_elems + 31) / 32 * 32;
+    p.bytes_per_unit = 2 * p.unit_stride * elem + 2 * p.max_b_elems * elem + 16;
+    int64_t sites = 0, bra = 0;
+    for (int q = 0; q < c.n; ++q) {
+        sites += p.site_elems[q];
+        bra += 2 * p.bra.cap[q];
+    }
+    p.bytes_per_bitstring = sites * elem + bra * 16 + p.bra_scratch_elems * 16 + c.n + 16;
+}
+
+}  // namespace tns

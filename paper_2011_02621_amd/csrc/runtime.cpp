@@ -1,0 +1,387 @@
+// Device runtime: allocation, plan upload, the resident ket evolution and the
+// batched amplitude executor.  Host code only orders launches; every
+// arithmetic step is a kernel (kernels_evolve.hip, kernels_contract.hip).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+
+#include "internal.h"
+
+namespace tns {
+
+static void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(TNS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dev_alloc(Ctx *ctx, size_t bytes, void *stream) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (ctx->alloc_fn) {
+        p = ctx->alloc_fn(bytes, stream, ctx->alloc_user);
+        if (!p) fail(TNS_E_OUT_OF_MEMORY, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(TNS_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    return p;
+}
+
+void dev_free(Ctx *ctx, void *p, void *stream) {
+    if (!p) return;
+    if (ctx->alloc_fn) ctx->free_fn(p, stream, ctx->alloc_user);
+    else (void)hipFree(p);
+}
+
+void *Workspace::get(Ctx *ctx, int slot, size_t need, void *stream) {
+    if ((int)bufs.size() <= slot) bufs.resize(slot + 1);
+    DeviceBuf &b = bufs[slot];
+    if (b.bytes < need) {
+        if (b.ptr) {
+            hip_check(hipStreamSynchronize((hipStream_t)stream), "workspace sync");
+            dev_free(ctx, b.ptr, stream);
+            bytes -= b.bytes;
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t grow = std::max(need, (size_t)256);
+        b.ptr = dev_alloc(ctx, grow, stream);
+        b.bytes = grow;
+        bytes += grow;
+        std::lock_guard<std::mutex> lk(ctx->mu_stats);
+        ctx->peak_bytes = std::max<int64_t>(ctx->peak_bytes, bytes);
+    }
+    return b.ptr;
+}
+
+void Workspace::release(Ctx *ctx, void *stream) {
+    if (!bufs.empty()) (void)hipStreamSynchronize((hipStream_t)stream);
+    for (auto &b : bufs) dev_free(ctx, b.ptr, stream);
+    bufs.clear();
+    bytes = 0;
+}
+
+static DeviceBuf upload(Ctx *ctx, const void *host, size_t bytes, void *stream) {
+    DeviceBuf b;
+    b.bytes = std::max<size_t>(bytes, 8);
+    b.ptr = dev_alloc(ctx, b.bytes, stream);
+    if (bytes)
+        hip_check(hipMemcpyAsync(b.ptr, host, bytes, hipMemcpyHostToDevice, (hipStream_t)stream),
+                  "upload");
+    return b;
+}
+
+// ----------------------------------------------------------------------------
+// one side of the evolution on `nb` copies (Eqs. (3)-(6))
+
+struct SideBuffers {
+    std::vector<double *> buf[2];   // per site, ping-pong
+    std::vector<int> cur;
+    std::vector<int64_t> stride;    // per site, complex elements per copy
+};
+
+static void run_side(const Plan &p, const SideEvolution &side, SideBuffers &sb, int64_t nb,
+                     double *vp, int64_t vp_stride, void *stream, int64_t &launches) {
+    const double *pq = (const double *)p.d_pq.ptr;
+    for (const EvoOp &op : side.ops) {
+        const double *P = pq + 64 * (int64_t)op.fused;
+        const double *Q = P + 32;
+        const int q0 = op.q0, q1 = op.q1;
+        launch::gate_apply(sb.buf[sb.cur[q0]][q0], sb.buf[1 - sb.cur[q0]][q0], nb, sb.stride[q0],
+                           sb.stride[q0], op.s0, op.leg0, op.chi, P, stream);
+        sb.cur[q0] ^= 1;
+        launch::gate_apply(sb.buf[sb.cur[q1]][q1], sb.buf[1 - sb.cur[q1]][q1], nb, sb.stride[q1],
+                           sb.stride[q1], op.s1, op.leg1, op.chi, Q, stream);
+        sb.cur[q1] ^= 1;
+        launches += 2;
+        if (op.comp < 0) continue;
+        const int k = op.comp == 0 ? q0 : q1, l = op.comp == 0 ? q1 : q0;
+        SiteShape sk = op.comp == 0 ? op.s0 : op.s1, sl = op.comp == 0 ? op.s1 : op.s0;
+        const int legk = op.comp == 0 ? op.leg0 : op.leg1, legl = op.comp == 0 ? op.leg1 : op.leg0;
+        sk.d[1 + legk] = op.d_grown;
+        sl.d[1 + legl] = op.d_grown;
+        launch::svd_compress(sb.buf[sb.cur[k]][k], sb.buf[1 - sb.cur[k]][k], vp, nb, sb.stride[k],
+                             sb.stride[k], vp_stride, sk, legk, stream);
+        sb.cur[k] ^= 1;
+        launch::absorb(sb.buf[sb.cur[l]][l], vp, sb.buf[1 - sb.cur[l]][l], nb, sb.stride[l], vp_stride,
+                       sb.stride[l], sl, legl, op.d_after, stream);
+        sb.cur[l] ^= 1;
+        launches += 2;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// plan setup: gate fusion + split on the device, resident ket
+
+void plan_device_setup(Ctx *ctx, Plan &p) {
+    void *st = ctx->stream;
+    const Circuit &c = p.circ;
+    std::vector<double> mats(c.gates.size() * 32);
+    for (size_t i = 0; i < c.gates.size(); ++i)
+        std::memcpy(&mats[32 * i], c.gates[i].m, 32 * sizeof(double));
+    p.d_mats = upload(ctx, mats.data(), mats.size() * 8, st);
+    p.d_chain = upload(ctx, p.chain_flat.data(), p.chain_flat.size() * 4, st);
+    p.d_chain_off = upload(ctx, p.chain_off.data(), p.chain_off.size() * 4, st);
+    p.d_chain_len = upload(ctx, p.chain_len.data(), p.chain_len.size() * 4, st);
+    p.d_fuse = upload(ctx, p.fuse.data(), p.fuse.size() * sizeof(FuseDesc), st);
+    DeviceBuf kc = upload(ctx, p.ket_init_chain.data(), p.ket_init_chain.size() * 4, st);
+    DeviceBuf bc = upload(ctx, p.bra_final_chain.data(), p.bra_final_chain.size() * 4, st);
+    p.d_pq.bytes = std::max<size_t>(p.fuse.size() * 64 * 8, 8);
+    p.d_pq.ptr = dev_alloc(ctx, p.d_pq.bytes, st);
+    p.d_ket_vec.bytes = c.n * 4 * 8;
+    p.d_ket_vec.ptr = dev_alloc(ctx, p.d_ket_vec.bytes, st);
+    p.d_bra_mat.bytes = c.n * 8 * 8;
+    p.d_bra_mat.ptr = dev_alloc(ctx, p.d_bra_mat.bytes, st);
+    launch::fuse_split((const double *)p.d_mats.ptr, (const int32_t *)p.d_chain.ptr,
+                       (const int32_t *)p.d_chain_off.ptr, (const int32_t *)p.d_chain_len.ptr,
+                       (const FuseDesc *)p.d_fuse.ptr, (int)p.fuse.size(), (double *)p.d_pq.ptr, c.n,
+                       (const int32_t *)kc.ptr, (const int32_t *)bc.ptr, (double *)p.d_ket_vec.ptr,
+                       (double *)p.d_bra_mat.ptr, st);
+
+    // ket evolution from |0...0> (with its leading single-qubit products)
+    SideBuffers sb;
+    sb.buf[0].resize(c.n);
+    sb.buf[1].resize(c.n);
+    sb.cur.assign(c.n, 0);
+    sb.stride.assign(p.ket.cap.begin(), p.ket.cap.end());
+    std::vector<DeviceBuf> bufs(2 * c.n);
+    for (int q = 0; q < c.n; ++q)
+        for (int h = 0; h < 2; ++h) {
+            bufs[2 * q + h].bytes = p.ket.cap[q] * 16;
+            bufs[2 * q + h].ptr = dev_alloc(ctx, bufs[2 * q + h].bytes, st);
+            sb.buf[h][q] = (double *)bufs[2 * q + h].ptr;
+        }
+    for (int q = 0; q < c.n; ++q) launch::init_ket((const double *)p.d_ket_vec.ptr, q, sb.buf[0][q], st);
+    DeviceBuf vp;
+    vp.bytes = std::max<int64_t>(p.bra_scratch_elems, 1) * 16;
+    vp.ptr = dev_alloc(ctx, vp.bytes, st);
+    int64_t launches = 0;
+    run_side(p, p.ket, sb, 1, (double *)vp.ptr, p.bra_scratch_elems, st, launches);
+    hip_check(hipStreamSynchronize((hipStream_t)st), "ket evolution");
+    p.ket_site.resize(c.n);
+    p.resident_bytes = 0;
+    for (int q = 0; q < c.n; ++q) {
+        p.ket_site[q] = bufs[2 * q + sb.cur[q]];
+        dev_free(ctx, bufs[2 * q + 1 - sb.cur[q]].ptr, st);
+        p.resident_bytes += p.ket_site[q].bytes;
+    }
+    dev_free(ctx, vp.ptr, st);
+    dev_free(ctx, kc.ptr, st);
+    dev_free(ctx, bc.ptr, st);
+
+    p.resident_bytes += p.d_mats.bytes + p.d_pq.bytes + p.d_fuse.bytes + p.d_chain.bytes;
+    hip_check(hipStreamSynchronize((hipStream_t)st), "plan upload");
+    p.ctx = ctx;
+    p.on_device = true;
+}
+
+void plan_device_release(Plan &p) {
+    if (!p.on_device || !p.ctx) return;
+    Ctx *ctx = p.ctx;
+    void *st = ctx->stream;
+    (void)hipDeviceSynchronize();
+    for (DeviceBuf *b : {&p.d_mats, &p.d_chain, &p.d_chain_off, &p.d_chain_len, &p.d_fuse, &p.d_pq,
+                         &p.d_ket_vec, &p.d_bra_mat}) {
+        dev_free(ctx, b->ptr, st);
+        b->ptr = nullptr;
+    }
+    for (auto &b : p.ket_site) dev_free(ctx, b.ptr, st);
+    p.ket_site.clear();
+    p.on_device = false;
+}
+
+// ----------------------------------------------------------------------------
+// executor
+
+int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget) {
+    // half of the budget for per-bitstring tensors, the rest for work units
+    int64_t per = p.bytes_per_bitstring + p.n_slices * 16 + 32;
+    int64_t nb = (int64_t)(budget / 2) / std::max<int64_t>(per, 1);
+    return std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+}
+
+enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_COUNT };
+
+namespace {
+struct Timer {
+    hipEvent_t e[2];
+    void *st;
+    bool on;
+    Timer(void *s, bool enable) : st(s), on(enable) {
+        if (on) {
+            (void)hipEventCreate(&e[0]);
+            (void)hipEventCreate(&e[1]);
+            (void)hipEventRecord(e[0], (hipStream_t)st);
+        }
+    }
+    double stop() {
+        if (!on) return 0;
+        (void)hipEventRecord(e[1], (hipStream_t)st);
+        (void)hipEventSynchronize(e[1]);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e[0], e[1]);
+        (void)hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[1]);
+        return ms;
+    }
+};
+}  // namespace
+
+void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
+                    double *amps_host, void *stream, Workspace &ws, RunStats &st,
+                    const volatile int *cancel, uint64_t budget) {
+    const Circuit &c = p.circ;
+    const bool c64 = p.precision != TNS_C128;
+    const int elem = c64 ? 8 : 16;
+    const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget));
+    const bool timing = true;
+
+    double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * 16, stream);
+    for (int64_t b0 = 0; b0 < n; b0 += nb_max) {
+        if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+        const int64_t nb = std::min(nb_max, n - b0);
+        uint8_t *bits_dev = (uint8_t *)ws.get(ctx, S_BITS, (size_t)nb * c.n, stream);
+        hip_check(hipMemcpyAsync(bits_dev, bits_host + b0 * c.n, (size_t)nb * c.n,
+                                 hipMemcpyHostToDevice, (hipStream_t)stream), "bits upload");
+
+        // ---- bra evolution, batched over bitstrings
+        Timer tb(stream, timing);
+        int64_t bra_total = 0;
+        for (int q = 0; q < c.n; ++q) bra_total += 2 * p.bra.cap[q];
+        double *bra = (double *)ws.get(ctx, S_BRA, (size_t)bra_total * nb * 16, stream);
+        double *vp = (double *)ws.get(ctx, S_VP, (size_t)std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16, stream);
+        SideBuffers sb;
+        sb.buf[0].resize(c.n);
+        sb.buf[1].resize(c.n);
+        sb.cur.assign(c.n, 0);
+        sb.stride.assign(p.bra.cap.begin(), p.bra.cap.end());
+        {
+            int64_t off = 0;
+            for (int q = 0; q < c.n; ++q)
+                for (int h = 0; h < 2; ++h) {
+                    sb.buf[h][q] = bra + 2 * off;
+                    off += p.bra.cap[q] * nb;
+                }
+        }
+        for (int q = 0; q < c.n; ++q)
+            launch::init_bra(bits_dev, c.n, nb, q, (const double *)p.d_bra_mat.ptr, sb.buf[0][q],
+                             p.bra.cap[q], stream);
+        st.launches += c.n;
+        run_side(p, p.bra, sb, nb, vp, p.bra_scratch_elems, stream, st.launches);
+        st.ms_bra += tb.stop();
+
+        // ---- overlap merge (Eq. (8))
+        Timer tm(stream, timing);
+        int64_t site_total = 0;
+        for (int q = 0; q < c.n; ++q) site_total += p.site_elems[q];
+        char *sites = (char *)ws.get(ctx, S_SITES, (size_t)site_total * nb * elem, stream);
+        std::vector<char *> site_ptr(c.n);
+        {
+            int64_t off = 0;
+            for (int q = 0; q < c.n; ++q) {
+                site_ptr[q] = sites + off * elem;
+                off += p.site_elems[q] * nb;
+            }
+        }
+        for (int q = 0; q < c.n; ++q)
+            launch::merge((const double *)p.ket_site[q].ptr, sb.buf[sb.cur[q]][q], site_ptr[q], nb,
+                          p.bra.cap[q], p.site_elems[q], p.ket.final_shape[q], p.bra.final_shape[q],
+                          c64 ? 1 : 0, stream);
+        st.launches += c.n;
+        st.ms_merge += tm.stop();
+
+        // ---- contraction of every (bitstring, slice) unit along the path
+        Timer tc(stream, timing);
+        const int64_t units = nb * p.n_slices;
+        double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * 16, stream);
+        const uint64_t used = ws.bytes;
+        const uint64_t left = budget > used ? budget - used : 0;
+        int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
+        G = std::max<int64_t>(1, std::min<int64_t>(G, units));
+        const int64_t peak = p.unit_stride;
+        char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
+        char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
+        char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
+        // optional per-class timing: events recorded around launches on this stream
+        struct Ev { hipEvent_t a, b; int cls; double flops, bytes; };
+        std::vector<Ev> evs;
+        auto ev_begin = [&](int cls, double fl, double by) {
+            if (!st.profile) return;
+            Ev e{};
+            (void)hipEventCreate(&e.a);
+            (void)hipEventCreate(&e.b);
+            e.cls = cls; e.flops = fl; e.bytes = by;
+            (void)hipEventRecord(e.a, (hipStream_t)stream);
+            evs.push_back(e);
+        };
+        auto ev_end = [&]() {
+            if (!st.profile) return;
+            (void)hipEventRecord(evs.back().b, (hipStream_t)stream);
+        };
+        for (int64_t ug0 = 0; ug0 < units; ug0 += G) {
+            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+            const int64_t g = std::min(G, units - ug0);
+            const Step &s0 = p.steps[0];
+            launch::gather_site(site_ptr[s0.site], X, g, ug0, p.n_slices, p.site_elems[s0.site],
+                                p.slice_map[s0.site],
+                                peak, s0.bgather, elem, stream);
+            char *cur = X;
+            st.launches += 1;
+            for (size_t m = 1; m < p.steps.size(); ++m) {
+                const Step &s = p.steps[m];
+                char *src = cur;
+                char *other = (cur == X) ? Y : X;
+                if (s.permute) {
+                    int64_t te = 1;
+                    for (int a = 0; a < s.perm.n; ++a) te *= s.perm.size[a];
+                    ev_begin(1, 0, 2.0 * elem * te * g);
+                    launch::gather(cur, other, g, peak, peak, s.perm, elem, stream);
+                    ev_end();
+                    src = other;
+                    st.launches += 1;
+                }
+                char *dst = (src == X) ? Y : X;
+                launch::build_b(site_ptr[s.site], Bb, g, ug0, p.n_slices, p.site_elems[s.site],
+                                p.slice_map[s.site],
+                                s.bgather, s.K, s.N, c64 ? 1 : 0, s.kernel == 0 ? 1 : 0, stream);
+                const double mkn = (double)s.M * s.K * s.N * g;
+                const double by = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
+                ev_begin(s.kernel == 0 ? 0 : 2, 8.0 * mkn, by);
+                if (s.kernel == 0)
+                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, c64 ? 1 : 0, stream);
+                else if (s.kernel == 1)
+                    launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
+                                           c64 ? 1 : 0, stream);
+                else
+                    launch::final_dot(src, Bb, partial + 2 * ug0, g, s.K, peak, s.K, c64 ? 1 : 0, stream);
+                ev_end();
+                st.launches += 2;
+                cur = dst;
+            }
+        }
+        launch::slice_sum(partial, amps_dev + 2 * b0, nb, p.n_slices, stream);
+        st.launches += 1;
+        st.ms_contract += tc.stop();
+        for (Ev &e : evs) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e.a, e.b);
+            if (e.cls == 0) { st.ms_gemm += ms; st.gemm_flops += e.flops; st.gemm_bytes += e.bytes; st.gemm_launches++; }
+            else if (e.cls == 1) { st.ms_permute += ms; st.permute_bytes += e.bytes; }
+            else st.ms_small += ms;
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        st.units += units;
+        st.flops += p.flops_per_amp * nb;
+    }
+    hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * 16, hipMemcpyDeviceToHost,
+                             (hipStream_t)stream), "amplitude download");
+    hip_check(hipStreamSynchronize((hipStream_t)stream), "amplitudes");
+}
+
+}  // namespace tns

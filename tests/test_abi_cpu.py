@@ -1,0 +1,197 @@
+"""Host-side tests of the C ABI (no GPU): symbol exports, planning-only
+contexts, error codes, bond-dimension pins of the paper and the path search
+against the oracle's brute force."""
+
+import re
+import os
+
+import numpy as np
+import pytest
+
+import paper_2011_02621_amd as T
+from circuits import CZ, fsim, grid, diagonal53, random_circuit, config
+from circuits.rqc import Circuit, Gate
+from oracle import paths
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(-1)
+    yield c
+    c.close()
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tns.h")).read()
+    declared = set(re.findall(r"^(?:tns_status|void|const char \*)\s*\n?\s*(tns_\w+)\(", header, re.M))
+    declared |= set(re.findall(r"\b(tns_\w+)\(", header)) - {"tns_gate", "tns_plan_info"}
+    lib = T.load_library()
+    assert declared, "no declarations parsed"
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(T.EXPORTED) <= declared
+
+
+def test_version():
+    assert "gfx950" in T.version()
+
+
+def test_planning_only_context_rejects_compute(ctx):
+    c, bits = config("grid3x4_d8")
+    p = ctx.plan(c, precision="c128")
+    with pytest.raises(T.TnsError) as e:
+        ctx.amplitudes(p, bits[:2])
+    assert e.value.name == "TNS_E_NO_DEVICE"
+
+
+def _two_qubit_circuit(n, edges, ops):
+    gates = [Gate(a, b, cyc, np.asarray(m, complex)) for a, b, cyc, m in ops]
+    return Circuit(n, edges, gates, 1)
+
+
+def test_bad_circuits(ctx):
+    good = _two_qubit_circuit(2, [(0, 1)], [(0, 1, 0, fsim(np.pi / 2, np.pi / 6))])
+    ctx.plan(good)
+    cases = {
+        "non-edge": _two_qubit_circuit(3, [(0, 1), (1, 2)], [(0, 2, 0, CZ)]),
+        "qubit range": _two_qubit_circuit(2, [(0, 1)], [(0, 5, 0, CZ)]),
+        "not unitary": _two_qubit_circuit(2, [(0, 1)], [(0, 1, 0, 2 * CZ)]),
+        "duplicate edge": _two_qubit_circuit(2, [(0, 1), (1, 0)], [(0, 1, 0, CZ)]),
+    }
+    for name, circ in cases.items():
+        with pytest.raises(T.TnsError) as e:
+            ctx.plan(circ)
+        assert e.value.name == "TNS_E_BAD_CIRCUIT", name
+
+
+def test_bad_path_and_cuts(ctx):
+    c, _ = config("grid3x4_d8")
+    with pytest.raises(T.TnsError) as e:
+        ctx.plan(c, path=[0] * 12)
+    assert e.value.name == "TNS_E_BAD_PATH"
+    with pytest.raises(T.TnsError) as e:
+        ctx.plan(c, cuts=[999])
+    assert e.value.name == "TNS_E_BAD_PATH"
+    with pytest.raises(T.TnsError) as e:
+        ctx.plan(c, split_cycle=99)
+    assert e.value.name == "TNS_E_INVALID_ARG"
+    with pytest.raises(T.TnsError) as e:
+        ctx.plan(c, precision="c64_bf16x3")
+    assert e.value.name == "TNS_E_UNSUPPORTED"
+
+
+def test_first_gate_compression_bond_is_two(ctx):
+    # Eq. (7): a qubit's first chi=4 gate leaves a bond of at most 2.
+    c = _two_qubit_circuit(4, [(0, 1), (1, 2), (2, 3)],
+                           [(0, 1, 0, fsim(np.pi / 2, np.pi / 6)), (2, 3, 0, fsim(np.pi / 2, np.pi / 6))])
+    p = ctx.plan(c, split_cycle=1)
+    i = p.info()
+    assert list(i.bond_ket) == [2, 1, 2]
+    assert list(i.bond_bra) == [1, 1, 1]
+
+
+def test_controlled_gate_has_rank_two(ctx):
+    # Eq. (2): chi_o = 2 for a controlled gate.  Two CZs on the same pair
+    # of fresh qubits: 2 then min(2*2, 2 * rest = 2) = 2.
+    c = _two_qubit_circuit(2, [(0, 1)], [(0, 1, 0, CZ), (0, 1, 0, CZ)])
+    assert list(ctx.plan(c, split_cycle=1).info().bond_ket) == [2]
+    # a chain: the middle qubit's bonds are not capped by a single leg
+    c = _two_qubit_circuit(3, [(0, 1), (1, 2)], [(0, 1, 0, CZ), (1, 2, 0, CZ), (0, 1, 0, CZ)])
+    assert list(ctx.plan(c, split_cycle=1).info().bond_ket) == [2, 2]
+
+
+def test_dcd_pattern_is_capped(ctx):
+    # gates on (k,l), (l,r), (k,l): the k-l bond would reach chi^2 = 16 but
+    # is capped at 2 * (rest of k) = 2 when k has no other bond.
+    f = fsim(np.pi / 2, np.pi / 6)
+    c = _two_qubit_circuit(3, [(0, 1), (1, 2)], [(0, 1, 0, f), (1, 2, 0, f), (0, 1, 0, f)])
+    i = ctx.plan(c, split_cycle=1).info()
+    assert i.bond_ket[0] == 2
+
+
+def test_overlap_bonds_multiply(ctx):
+    c, _ = config("grid3x4_d8")
+    i = ctx.plan(c, split_cycle=4).info()
+    assert np.array_equal(i.bond_overlap, i.bond_ket * i.bond_bra)
+
+
+def test_plan_info_consistency(ctx):
+    c, _ = config("grid5x5_d10")
+    i = ctx.plan(c, precision="c64").info()
+    assert sorted(i.path.tolist()) == list(range(25))
+    assert len(i.step_m) == 24
+    flops = 8 * np.sum(i.step_m.astype(float) * i.step_k * i.step_n) * i.n_slices
+    assert flops == pytest.approx(i.flops_per_amp)
+    assert i.step_m[-1] == 1 and i.step_n[-1] == 1 and i.step_kernel[-1] == 2
+    # the reported score is the oracle's score of the same order
+    dims = [float(d) for d in i.bond_overlap]
+    s, peak = paths.score(i.path.tolist(), c.n, c.edges, dims)
+    assert s == pytest.approx(i.path_score) and peak == i.peak_elems
+
+
+def test_fidelity_reported(ctx):
+    c, _ = config("diag53_d12", final_layer=False)
+    i = ctx.plan(c, split_cycle=6, path_mode="greedy", max_intermediate_elems=1 << 60).info()
+    assert i.fidelity == pytest.approx(9.314e-3, abs=5e-6)
+
+
+def test_explicit_cuts_multiply_slices(ctx):
+    c, _ = config("grid3x4_d8")
+    i0 = ctx.plan(c, split_cycle=4).info()
+    i1 = ctx.plan(c, split_cycle=4, cuts=[3, 10]).info()
+    assert i1.n_slices == i0.bond_overlap[3] * i0.bond_overlap[10]
+    assert list(i1.cut_edges) == [3, 10]
+
+
+def test_automatic_cuts_respect_limit(ctx):
+    c, _ = config("grid5x5_d10")
+    i = ctx.plan(c, precision="c64", max_intermediate_elems=1 << 18).info()
+    assert i.peak_elems <= 1 << 18 and i.n_slices > 1
+
+
+# --- path search vs brute force (supplement, Algorithm 1 and Eq. (optscore))
+
+def _random_graph(seed, n):
+    rng = np.random.default_rng(seed)
+    edges = set()
+    for q in range(1, n):
+        edges.add((int(rng.integers(q)), q))
+    while len(edges) < n + 2:
+        a, b = sorted(rng.choice(n, 2, replace=False))
+        edges.add((int(a), int(b)))
+    edges = sorted(edges)
+    dims = [float(2 ** rng.integers(1, 5)) for _ in edges]
+    return edges, dims
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_algorithm1_without_assumptions_is_optimal(seed):
+    n = 7
+    edges, dims = _random_graph(seed, n)
+    best, _ = paths.brute_force(n, edges, dims)
+    order, score = T.path_search(n, edges, dims, mode="algorithm1", assumptions=False)
+    assert sorted(order) == list(range(n))
+    assert paths.score(order, n, edges, dims)[0] == score
+    assert score == best
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_restricted_searches_are_admissible(seed):
+    n = 8
+    edges, dims = _random_graph(100 + seed, n)
+    best, _ = paths.brute_force(n, edges, dims)
+    for mode in ("algorithm1", "greedy"):
+        order, score = T.path_search(n, edges, dims, mode=mode, assumptions=True)
+        assert sorted(order) == list(range(n))
+        assert paths.score(order, n, edges, dims)[0] == score >= best
+
+
+def test_algorithm1_grid_beats_or_ties_greedy():
+    g = grid(4, 4)
+    rng = np.random.default_rng(3)
+    dims = [float(2 ** rng.integers(2, 5)) for _ in g.edges]
+    _, s1 = T.path_search(g.n, g.edges, dims, mode="algorithm1")
+    _, sg = T.path_search(g.n, g.edges, dims, mode="greedy")
+    assert s1 <= sg

@@ -1,0 +1,162 @@
+"""GPU parity: amplitudes through the C ABI against the CPU oracle.
+
+Tolerances (the paper states none; the requirement is relative error <= 1e-10
+for complex128 and <= 1e-4 for complex64): rel_l2 = ||b - a|| / ||a|| over the
+batch, plus max |b_i - a_i| / rms(a) <= 10 x the tolerance.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2011_02621_amd as T
+from circuits import config, grid, diagonal53, random_circuit, mirror_circuit, bitstrings
+from oracle import sv, stabilizer
+from oracle.metrics import compare
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-4}
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def check(ref, got, n, prec):
+    m = compare(ref, got, n)
+    tol = TOL[prec]
+    assert m["rel_l2"] <= tol, m
+    assert m["max_scaled"] <= 10 * tol, m
+    return m
+
+
+@pytest.fixture(scope="module")
+def small():
+    c, bits = config("grid3x4_d8")
+    return c, bits, sv.amplitudes(c, bits)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_grid3x4_all_bitstrings(ctx, small, prec):
+    c, bits, ref = small
+    say("grid3x4_d8", prec, bits.shape)
+    p = ctx.plan(c, precision=prec)
+    got = ctx.amplitudes(p, bits)
+    check(ref, got, c.n, prec)
+
+
+def test_grid3x4_every_split_is_exact(ctx, small):
+    c, bits, ref = small
+    for k in range(0, c.depth + 1):
+        say("grid3x4_d8 split", k)
+        p = ctx.plan(c, split_cycle=k, precision="c128")
+        got = ctx.amplitudes(p, bits[:16])
+        assert compare(ref[:16], got, c.n)["rel_l2"] <= 1e-12
+
+
+def test_grid3x4_paths_and_cuts_agree(ctx, small):
+    c, bits, ref = small
+    rng = np.random.default_rng(0)
+    variants = [dict(path_mode="greedy"), dict(path_mode="algorithm1"),
+                dict(path=list(rng.permutation(c.n))), dict(cuts=[2, 9]), dict(cuts=[0, 5, 11]),
+                dict(max_intermediate_elems=1 << 8)]
+    for v in variants:
+        say("grid3x4_d8 variant", v)
+        p = ctx.plan(c, split_cycle=4, precision="c128", **v)
+        got = ctx.amplitudes(p, bits)
+        assert compare(ref, got, c.n)["rel_l2"] <= 1e-12, v
+
+
+def test_no_final_layer(ctx):
+    c, bits = config("grid3x4_d8", final_layer=False)
+    ref = sv.amplitudes(c, bits)
+    for k in (0, 5, 8):
+        say("grid3x4_d8 no final layer split", k)
+        got = ctx.amplitudes(ctx.plan(c, split_cycle=k), bits)
+        check(ref, got, c.n, "c128")
+
+
+def test_norm_by_enumeration(ctx):
+    c = random_circuit(grid(3, 4), 6, 77)
+    allbits = np.array([[(i >> (11 - q)) & 1 for q in range(12)] for i in range(4096)], np.uint8)
+    say("grid3x4 d6 all 4096 bitstrings")
+    got = ctx.amplitudes(ctx.plan(c, precision="c128"), allbits)
+    assert abs(np.sum(np.abs(got) ** 2) - 1) < 1e-11
+
+
+def test_mirror_small(ctx):
+    c = mirror_circuit(grid(3, 4), 4, 5)
+    bits = np.vstack([np.zeros((1, 12), np.uint8), bitstrings(12, 15, 3)])
+    say("mirror 3x4")
+    got = ctx.amplitudes(ctx.plan(c, split_cycle=4), bits)
+    assert abs(got[0] - 1) < 1e-12
+    assert np.abs(got[1:][bits[1:].any(axis=1)]).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_grid5x5_d10(ctx, prec):
+    c, bits = config("grid5x5_d10")
+    n = 48 if prec == "c128" else 256
+    bits = bits[:n]
+    say("grid5x5_d10", prec, n, "oracle...")
+    ref = sv.amplitudes(c, bits)
+    say("grid5x5_d10", prec, "plan + contract")
+    p = ctx.plan(c, precision=prec)
+    got = ctx.amplitudes(p, bits)
+    check(ref, got, c.n, prec)
+
+
+def test_mirror_53(ctx):
+    c = mirror_circuit(diagonal53(), 3, 8)
+    bits = np.vstack([np.zeros((1, 53), np.uint8), bitstrings(53, 3, 4)])
+    say("mirror diag53 3+3")
+    got = ctx.amplitudes(ctx.plan(c, split_cycle=3, precision="c128"), bits)
+    assert abs(got[0] - 1) < 1e-10
+    assert np.abs(got[1:]).max() < 1e-10
+
+
+def test_clifford_53_against_tableau(ctx):
+    c = random_circuit(diagonal53(), 6, 13, clifford=True)
+    bits = bitstrings(53, 8, 14)
+    say("clifford diag53 d6")
+    p_ref = stabilizer.probabilities(c, bits)
+    got = ctx.amplitudes(ctx.plan(c, precision="c128"), bits)
+    assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 1e-10 * max(p_ref.max(), 2.0 ** -53)
+
+
+def test_stream_argument(ctx, small):
+    import torch
+    c, bits, ref = small
+    s = torch.cuda.Stream()
+    say("explicit torch stream")
+    got = ctx.amplitudes(ctx.plan(c), bits, stream=s.cuda_stream)
+    check(ref, got, c.n, "c128")
+
+
+def test_serving_equivalence(ctx, small):
+    c, bits, ref = small
+    c2, bits2 = config("grid5x5_d10", n_bits=24)
+    p1 = ctx.plan(c, precision="c64")
+    p2 = ctx.plan(c2, precision="c64")
+    alone1 = ctx.amplitudes(p1, bits)
+    alone2 = ctx.amplitudes(p2, bits2)
+    say("serving mix")
+    reqs = []
+    for i in range(6):
+        reqs.append(ctx.submit(p2, bits2))
+        reqs.append(ctx.submit(p1, bits))
+    outs = [r.wait() for r in reqs]
+    for i, o in enumerate(outs):
+        want = alone2 if i % 2 == 0 else alone1
+        assert np.array_equal(o, want)
+    check(ref, outs[1], c.n, "c64")
