@@ -239,7 +239,7 @@ class Request:
 
     def wait(self) -> np.ndarray:
         _check(load_library().tns_wait(self._h))
-        return self.amps.view(np.complex128)
+        return self.amps.view(np.complex128).reshape(-1)
 
     def cancel(self):
         _check(load_library().tns_cancel(self._h))

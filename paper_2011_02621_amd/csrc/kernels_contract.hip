@@ -262,14 +262,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
-    // 16x16 f64 accumulator layout: lane holds column lane%16 and rows 4*(lane/16) + r.
+    // 16x16 f64 accumulator layout: lane holds column lane%16 and rows lane/16 + 4*r.
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
             }

@@ -64,12 +64,25 @@ def test_grid3x4_every_split_is_exact(ctx, small):
         assert compare(ref[:16], got, c.n)["rel_l2"] <= 1e-12
 
 
+def random_connected_order(n, edges, seed):
+    rng = np.random.default_rng(seed)
+    nbr = {q: set() for q in range(n)}
+    for a, b in edges:
+        nbr[a].add(b)
+        nbr[b].add(a)
+    order = [int(rng.integers(n))]
+    while len(order) < n:
+        front = sorted({x for q in order for x in nbr[q]} - set(order))
+        order.append(int(front[int(rng.integers(len(front)))]))
+    return order
+
+
 def test_grid3x4_paths_and_cuts_agree(ctx, small):
     c, bits, ref = small
-    rng = np.random.default_rng(0)
     variants = [dict(path_mode="greedy"), dict(path_mode="algorithm1"),
-                dict(path=list(rng.permutation(c.n))), dict(cuts=[2, 9]), dict(cuts=[0, 5, 11]),
-                dict(max_intermediate_elems=1 << 8)]
+                dict(path=random_connected_order(c.n, c.edges, 0)),
+                dict(path=random_connected_order(c.n, c.edges, 1)),
+                dict(cuts=[2, 9]), dict(cuts=[0, 5, 11]), dict(max_intermediate_elems=1 << 8)]
     for v in variants:
         say("grid3x4_d8 variant", v)
         p = ctx.plan(c, split_cycle=4, precision="c128", **v)
