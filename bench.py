@@ -23,7 +23,9 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # FP32 / FP64 dense MFMA, MI355X
+# dense MFMA peaks of MI355X: FP32, FP64; split-BF16 GEMMs are priced against
+# the FP32 peak for the same algorithmic (complex64) flops
+PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "c64_bf16x3": 157.3, "c64_bf16x6": 157.3}
 PEAK_HBM_GBS = 8000.0
 
 
@@ -80,7 +82,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid5x5_d10")
-    ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--precision", default="c64", choices=["c64", "c128", "c64_bf16x3", "c64_bf16x6"])
     ap.add_argument("--bits", type=int, default=0, help="bitstrings per step (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -127,7 +129,9 @@ def main():
 
     gemm_tflops = agg["gemm_flops"] / (agg["ms_gemm"] * 1e-3) / 1e12 if agg.get("ms_gemm") else 0.0
     avg_gemm_ms = agg["ms_gemm"] / max(agg["gemm_launches"], 1)
-    roofline = {"bound": "mfma", "kernel": "k_gemm_f32" if args.precision == "c64" else "k_gemm_f64",
+    kname = {"c64": "k_gemm_f32", "c128": "k_gemm_f64", "c64_bf16x3": "k_gemm_bf16<2>",
+             "c64_bf16x6": "k_gemm_bf16<3>"}[args.precision]
+    roofline = {"bound": "mfma", "kernel": kname,
                 "achieved": round(gemm_tflops, 3), "peak": PEAK_TFLOPS[args.precision],
                 "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_TFLOPS[args.precision], 4),
                 "traffic": None, "avg_launch_ms": round(avg_gemm_ms, 4),
@@ -151,6 +155,16 @@ def main():
         a1 = amps[:len(sub)]
         ref, test = (a2, a1) if other == "c128" else (a1, a2)
         extra[f"{other}_amps_per_s"] = round(len(sub) / t2, 3)
+        if args.precision == "c64":
+            for sp in ("c64_bf16x3", "c64_bf16x6"):
+                p3 = ctx.plan(circ, precision=sp)
+                ctx.amplitudes(p3, sub[:4])
+                t = time.perf_counter()
+                a3 = ctx.amplitudes(p3, sub)
+                t3 = time.perf_counter() - t
+                extra[sp] = {"amps_per_s": round(len(sub) / t3, 3), "rel_l2_vs_c128": rel_l2(a2, a3),
+                             "f_xeb": xeb(a2, a3, n_q)}
+                p3.close()
         extra["c64_vs_c128"] = {"rel_l2": rel_l2(ref, test),
                                 "max_scaled": float(np.abs(test - ref).max() / (np.linalg.norm(ref) / np.sqrt(len(ref)))),
                                 "f_xeb": xeb(ref, test, n_q),
@@ -193,7 +207,8 @@ def main():
         "value": round(value, 4), "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 (fp32 mfma)" if args.precision == "c64" else "c128 (fp64 mfma)",
+        "dtype": {"c64": "c64 (fp32 mfma)", "c128": "c128 (fp64 mfma)",
+                  "c64_bf16x3": "c64 (split-bf16 x3)", "c64_bf16x6": "c64 (split-bf16 x6)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "qubits": n_q, "cycles": circ.depth,
                    "bitstrings_per_step": int(len(bits)), "precision": args.precision,

@@ -306,7 +306,7 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
              int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream);
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
-          int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64, void *stream);
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream);
 void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
                     int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
                     void *stream);

@@ -63,6 +63,58 @@ __global__ void k_gather(const E *__restrict__ in, E *__restrict__ out, int64_t 
     }
 }
 
+// LDS-tiled permute.  The output is row-major over g.size; g.stride gives
+// each output axis's input stride.  Axis ai is the input-contiguous axis
+// (input stride 1) and axis ao the output-contiguous one (the last output
+// axis); a tile covers up to 64 x 64 (ai, ao) positions and is read along ai
+// (coalesced reads), staged in LDS and written along ao (coalesced writes).
+// Every other axis, and the unit, is one coordinate of the tile index.
+struct PermTile {
+    int32_t n;                 // axes
+    int32_t ai, ao;            // input- and output-contiguous axes
+    int32_t ti, to;            // tile extents along ai and ao
+    int64_t size[kMaxGatherDims];
+    int64_t in_stride[kMaxGatherDims];
+    int64_t out_stride[kMaxGatherDims];
+    int64_t tiles_i, tiles_o;  // tiles along ai and ao
+    int64_t tiles_per_unit;
+};
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_permute_tiled(const E *__restrict__ in, E *__restrict__ out,
+                                                        int64_t units, int64_t in_us, int64_t out_us,
+                                                        PermTile pt) {
+    __shared__ E tile[64 * 65];
+    const int64_t total = pt.tiles_per_unit * units;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int64_t u = t / pt.tiles_per_unit;
+        int64_t r = t - u * pt.tiles_per_unit;
+        const int64_t tio = r % pt.tiles_o; r /= pt.tiles_o;
+        const int64_t tii = r % pt.tiles_i; r /= pt.tiles_i;
+        int64_t base_in = u * in_us, base_out = u * out_us;
+        for (int a = pt.n - 1; a >= 0; --a) {
+            if (a == pt.ai || a == pt.ao) continue;
+            const int64_t c = r % pt.size[a];
+            r /= pt.size[a];
+            base_in += c * pt.in_stride[a];
+            base_out += c * pt.out_stride[a];
+        }
+        const int64_t i0 = tii * pt.ti, o0 = tio * pt.to;
+        const int ni = (int)min<int64_t>(pt.ti, pt.size[pt.ai] - i0);
+        const int no = (int)min<int64_t>(pt.to, pt.size[pt.ao] - o0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < ni * no; e += 256) {
+            const int o = e / ni, i = e - o * ni;
+            tile[o * 65 + i] = in[base_in + (i0 + i) + (o0 + o) * pt.in_stride[pt.ao]];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ni * no; e += 256) {
+            const int i = e / no, o = e - i * no;
+            out[base_out + (o0 + o) + (i0 + i) * pt.out_stride[pt.ai]] = tile[o * 65 + i];
+        }
+    }
+}
+
 // unit u of this launch is global unit ug = u0 + u = bitstring * n_slices + slice
 template <typename E>
 __global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, int64_t units,
@@ -276,6 +328,123 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
+// Split-BF16 compensated GEMM: each FP32 operand x is split by round-to-
+// nearest-even into bf16 parts, x = hi + lo (+ mid), and the product is
+// summed from the significant part products on the BF16 MFMA cores with FP32
+// accumulation:  NSPLIT = 2: hi*hi + hi*lo + lo*hi (3 products);
+//                NSPLIT = 3: hi*hi + hi*mid + mid*hi + hi*lo + mid*mid + lo*hi (6).
+// Operands are read as FP32 from HBM and split while being staged into LDS.
+// Same tiling as the FP32 kernel: 128 x 128 tile, k-step 32, four waves of
+// 64 x 64, v_mfma_f32_32x32x16_bf16 (a lane supplies 8 consecutive k of its
+// row / column; A and B use the same k assignment, so the sum is exact in k).
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BF_BM = 128, BF_BN = 128, BF_BK = 32, BF_LD = BF_BK + 8;
+
+template <int NSPLIT>
+__device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v) {
+    bf16x4 h, m, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float x = v[e];
+        const __bf16 a = (__bf16)x;
+        const float r1 = x - (float)a;
+        const __bf16 b = (__bf16)r1;
+        h[e] = a;
+        m[e] = b;
+        if (NSPLIT == 3) l[e] = (__bf16)(r1 - (float)b);
+    }
+    *reinterpret_cast<bf16x4 *>(dst) = h;
+    *reinterpret_cast<bf16x4 *>(dst + part_stride) = m;
+    if (NSPLIT == 3) *reinterpret_cast<bf16x4 *>(dst + 2 * part_stride) = l;
+}
+
+template <int NSPLIT>
+__global__ __launch_bounds__(256) void k_gemm_bf16(const float *__restrict__ A,
+                                                    const float *__restrict__ Bt,
+                                                    float *__restrict__ C, int64_t M, int Kr,
+                                                    int Nr, int64_t sA, int64_t sB, int64_t sC,
+                                                    int tiles_n) {
+    constexpr int PART = BF_BM * BF_LD;   // elements per split part
+    __shared__ __bf16 As[NSPLIT * PART];
+    __shared__ __bf16 Bs[NSPLIT * PART];
+    const int64_t u = blockIdx.y;
+    const int64_t tile = blockIdx.x;
+    const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+    const int64_t m0 = tm * BF_BM;
+    const int n0 = (int)tn * BF_BN;
+    A += u * sA;
+    Bt += u * sB;
+    C += u * sC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    v16f acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int lrow = tid >> 3, lcol = (tid & 7) * 4;
+    for (int k0 = 0; k0 < Kr; k0 += BF_BK) {
+        const int gk = k0 + lcol;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = lrow + 32 * i;
+            const int64_t gm = m0 + row;
+            v4f va = {0.f, 0.f, 0.f, 0.f};
+            if (gm < M && gk < Kr) va = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
+            split_store<NSPLIT>(&As[row * BF_LD + lcol], PART, va);
+            const int gn = n0 + row;
+            v4f vb = {0.f, 0.f, 0.f, 0.f};
+            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
+            split_store<NSPLIT>(&Bs[row * BF_LD + lcol], PART, vb);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BF_BK; kk += 16) {
+            const int kofs = kk + 8 * (lane >> 5);
+            bf16x8 a[2][NSPLIT], b[2][NSPLIT];
+#pragma unroll
+            for (int p = 0; p < NSPLIT; ++p) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    a[i][p] = *reinterpret_cast<const bf16x8 *>(
+                        &As[p * PART + (wm * 64 + i * 32 + (lane & 31)) * BF_LD + kofs]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    b[j][p] = *reinterpret_cast<const bf16x8 *>(
+                        &Bs[p * PART + (wn * 64 + j * 32 + (lane & 31)) * BF_LD + kofs]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    // smallest terms first
+                    if (NSPLIT == 3) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], acc[i][j], 0, 0, 0);
+                    }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // small steps: one thread per output element, C[u][m][n] = sum_k A[u][m][k] B[u][n][k]
 
 template <typename R, typename Acc>
@@ -379,6 +548,41 @@ void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
     int64_t per = 1;
     for (int a = 0; a < g.n; ++a) per *= g.size[a];
     const int64_t total = per * units;
+    // tiled transpose when the input- and output-contiguous axes differ
+    int ai = -1;
+    for (int a = 0; a < g.n; ++a)
+        if (g.stride[a] == 1 && g.size[a] > 1) ai = a;
+    const int ao = g.n - 1;
+    if (ai >= 0 && ai != ao && g.size[ai] >= 8 && g.size[ao] >= 8) {
+        PermTile pt{};
+        pt.n = g.n;
+        pt.ai = ai;
+        pt.ao = ao;
+        int64_t os = 1;
+        for (int a = g.n - 1; a >= 0; --a) {
+            pt.size[a] = g.size[a];
+            pt.in_stride[a] = g.stride[a];
+            pt.out_stride[a] = os;
+            os *= g.size[a];
+        }
+        pt.ti = (int)std::min<int64_t>(64, g.size[ai]);
+        pt.to = (int)std::min<int64_t>(64, g.size[ao]);
+        pt.tiles_i = (g.size[ai] + pt.ti - 1) / pt.ti;
+        pt.tiles_o = (g.size[ao] + pt.to - 1) / pt.to;
+        pt.tiles_per_unit = per / (g.size[ai] * g.size[ao]) * pt.tiles_i * pt.tiles_o;
+        const int64_t tiles = pt.tiles_per_unit * units;
+        const unsigned blocks = (unsigned)std::min<int64_t>(tiles, 65536 * 8);
+        if (elem_bytes == 8)
+            hipLaunchKernelGGL(k_permute_tiled<float2>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                               (const float2 *)in, (float2 *)out, units, in_unit_stride,
+                               out_unit_stride, pt);
+        else
+            hipLaunchKernelGGL(k_permute_tiled<double2>, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                               (const double2 *)in, (double2 *)out, units, in_unit_stride,
+                               out_unit_stride, pt);
+        check_launch("permute");
+        return;
+    }
     if (elem_bytes == 8)
         hipLaunchKernelGGL(k_gather<float2>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const float2 *)in, (float2 *)out, units,
@@ -423,10 +627,14 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
 }
 
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
-          int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64, void *stream) {
-    // strides arrive in complex elements; the kernels index reals
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream) {
+    // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
+    // split-BF16 MFMA with 3 / 6 products.  Strides arrive in complex elements;
+    // the kernels index reals.
+    const int c64 = mode != 0;
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
+    static_assert(BF_BM == F32_BM && BF_BN == F32_BN, "split-bf16 and FP32 tiles agree");
     const int BM = c64 ? F32_BM : F64_BM, BN = c64 ? F32_BN : F64_BN;
     const int tiles_n = (Nr + BN - 1) / BN;
     // rows per launch so that the grid stays below 2^31 blocks
@@ -438,7 +646,14 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
             const int64_t mr = std::min<int64_t>(rows_per, M - r0);
             const int64_t tiles_m = (mr + BM - 1) / BM;
             const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)nu);
-            if (c64)
+            if (mode == 2 || mode == 3) {
+                auto kern = mode == 2 ? k_gemm_bf16<2> : k_gemm_bf16<3>;
+                hipLaunchKernelGGL(kern, grid, dim3(256), 0, (hipStream_t)stream,
+                                   (const float *)A + 2 * (u0 * sA + r0 * K),
+                                   (const float *)Bt + 4 * u0 * sB,
+                                   (float *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
+                                   2 * sC, tiles_n);
+            } else if (c64)
                 hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, (hipStream_t)stream,
                                    (const float *)A + 2 * (u0 * sA + r0 * K),
                                    (const float *)Bt + 4 * u0 * sB,

@@ -910,8 +910,6 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
     p.precision = opts.precision;
     if (opts.precision < TNS_C128 || opts.precision > TNS_C64_SPLIT_BF16_6)
         fail(TNS_E_INVALID_ARG, "unknown precision");
-    if (opts.precision >= TNS_C64_SPLIT_BF16_3)
-        fail(TNS_E_UNSUPPORTED, "split-bf16 contraction is not available in this build");
     if (opts.n_open != 0 || opts.open_qubits) fail(TNS_E_UNSUPPORTED, "open qubits are reserved");
     if (opts.path) {
         std::vector<char> seen(c.n, 0);

@@ -302,7 +302,9 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         const uint64_t used = ws.bytes;
         const uint64_t left = budget > used ? budget - used : 0;
         int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
-        G = std::max<int64_t>(1, std::min<int64_t>(G, units));
+        // enough units per launch to fill the chip; more only costs memory
+        const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 27) / std::max<int64_t>(p.unit_stride, 1));
+        G = std::max<int64_t>(1, std::min<int64_t>(std::min(G, fill), units));
         const int64_t peak = p.unit_stride;
         char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
         char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
@@ -353,7 +355,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 const double by = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
                 ev_begin(s.kernel == 0 ? 0 : 2, 8.0 * mkn, by);
                 if (s.kernel == 0)
-                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, c64 ? 1 : 0, stream);
+                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream);
                 else if (s.kernel == 1)
                     launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
                                            c64 ? 1 : 0, stream);

@@ -77,9 +77,6 @@ def test_bad_path_and_cuts(ctx):
     with pytest.raises(T.TnsError) as e:
         ctx.plan(c, split_cycle=99)
     assert e.value.name == "TNS_E_INVALID_ARG"
-    with pytest.raises(T.TnsError) as e:
-        ctx.plan(c, precision="c64_bf16x3")
-    assert e.value.name == "TNS_E_UNSUPPORTED"
 
 
 def test_first_gate_compression_bond_is_two(ctx):
