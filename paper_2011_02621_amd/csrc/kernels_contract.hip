@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -60,6 +61,46 @@ __global__ void k_gather(const E *__restrict__ in, E *__restrict__ out, int64_t 
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t u = t / per, i = t - u * per;
         out[u * out_us + i] = in[u * in_us + gather_offset(g, i)];
+    }
+}
+
+// Strided gather with 32-bit index arithmetic (64-bit integer division is a
+// long instruction sequence on CDNA), valid when one unit holds fewer than
+// 2^31 elements (the launcher checks).  Units come from blockIdx.y.  With
+// VEC = 2 (complex64, output-fastest axis contiguous in the input and of even
+// size) each copy moves two elements with one 16-byte load and store; every
+// thread keeps four copies in flight.
+template <typename E, int VEC>
+__global__ __launch_bounds__(256) void k_gather32(const E *__restrict__ in, E *__restrict__ out,
+                                                   int64_t in_us, int64_t out_us, Gather g,
+                                                   uint32_t per) {
+    using V = typename std::conditional<VEC == 2, float4, E>::type;
+    const int n = g.n;
+    const E *src = in + blockIdx.y * in_us;
+    E *dst = out + blockIdx.y * out_us;
+    const uint32_t nv = per / VEC;
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t v0 = blockIdx.x * blockDim.x + threadIdx.x; v0 < nv; v0 += 4 * step) {
+        V val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t v = v0 + u * step;
+            if (v < nv) {
+                uint32_t r = v * VEC, off = 0;
+                for (int a = n - 1; a >= 0; --a) {
+                    const uint32_t sz = (uint32_t)g.size[a];
+                    const uint32_t q = r / sz;
+                    off += (r - q * sz) * (uint32_t)g.stride[a];
+                    r = q;
+                }
+                val[u] = *reinterpret_cast<const V *>(src + off);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t v = v0 + u * step;
+            if (v < nv) *reinterpret_cast<V *>(dst + (size_t)v * VEC) = val[u];
+        }
     }
 }
 
@@ -178,75 +219,190 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-constexpr int F32_BM = 128, F32_BN = 128, F32_BK = 32, F32_LD = F32_BK + 4;
+constexpr int G_BK = 32;   // k-step (reals) of the FP32 and split-BF16 kernels
 
-__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A,
+// Tile order: consecutive workgroup ids are dispatched round-robin over the
+// 8 XCDs, each with its own L2.  Remap so that each XCD receives a contiguous
+// run of logical tiles (row-major over (tile_m, tile_n)), i.e. the tiles that
+// share rows of A, and so their A reads, stay on one XCD.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
+    const int64_t per = ntiles / 8;
+    if (per == 0) return b;
+    const int64_t main = per * 8;
+    if (b >= main) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Split-BF16: each FP32 operand x is split by round-to-nearest-even into bf16
+// parts, x = hi + mid (+ lo), and the product is summed from the significant
+// part products on the BF16 MFMA cores with FP32 accumulation:
+//   NSPLIT = 2: hi*hi + hi*mid + mid*hi                          (3 products)
+//   NSPLIT = 3: the same plus hi*lo + mid*mid + lo*hi            (6 products)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+template <int NSPLIT>
+__device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v) {
+    bf16x4 h, m, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float x = v[e];
+        const __bf16 a = (__bf16)x;
+        const float r1 = x - (float)a;
+        const __bf16 b = (__bf16)r1;
+        h[e] = a;
+        m[e] = b;
+        if (NSPLIT == 3) l[e] = (__bf16)(r1 - (float)b);
+    }
+    *reinterpret_cast<bf16x4 *>(dst) = h;
+    *reinterpret_cast<bf16x4 *>(dst + part_stride) = m;
+    if (NSPLIT == 3) *reinterpret_cast<bf16x4 *>(dst + 2 * part_stride) = l;
+}
+
+// C[M][Nr] = A[M][Kr] * Bt[Nr][Kr]^T, row-major, Kr % 4 == 0.  256 threads =
+// 4 waves in a WGM x WGN layout; each wave owns BI x BJ blocks of 32 x 32, so
+// the tile is (WGM*BI*32) x (WGN*BJ*32), k-step 32.  The next k-tile is
+// fetched into registers while the current one is multiplied out of LDS.
+// MODE 1: FP32 operands, v_mfma_f32_32x32x2f32; the two k-slots of an MFMA
+// (lanes 0-31 / 32-63) take k = 4*slot + t for the four MFMAs t of an
+// 8-wide k group, so each lane reads its values with one 16-byte LDS load.
+// MODE 2 / 3: split-BF16 with 3 / 6 products, v_mfma_f32_32x32x16_bf16, a
+// lane supplying 8 consecutive k of its row (A) and of its column (B).
+template <int BI, int BJ, int WGM, int WGN, int MODE>
+__global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                                                    const float *__restrict__ Bt,
-                                                   float *__restrict__ C, int64_t M, int Kr,
-                                                   int Nr, int64_t sA, int64_t sB, int64_t sC,
-                                                   int tiles_n) {
-    __shared__ float As[F32_BM * F32_LD];
-    __shared__ float Bs[F32_BN * F32_LD];
+                                                   float *__restrict__ C, int64_t M, int Kr, int Nr,
+                                                   int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+    static_assert(WGM * WGN == 4, "four waves");
+    constexpr int BM = WGM * BI * 32, BN = WGN * BJ * 32;
+    constexpr int NSPLIT = MODE == 1 ? 1 : MODE;          // 1, 2 or 3 parts
+    constexpr int LD = MODE == 1 ? G_BK + 4 : G_BK + 8;   // padded row (elements)
+    using ET = typename std::conditional<MODE == 1, float, __bf16>::type;
+    constexpr int APART = BM * LD, BPART = BN * LD;
+    __shared__ ET As[NSPLIT * APART];
+    __shared__ ET Bs[NSPLIT * BPART];
+    constexpr int AV = BM / 32, BV = BN / 32;   // float4 loads per thread
     const int64_t u = blockIdx.y;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
-    const int64_t m0 = tm * F32_BM;
-    const int n0 = (int)tn * F32_BN;
+    const int64_t m0 = tm * BM;
+    const int n0 = (int)tn * BN;
     A += u * sA;
     Bt += u * sB;
     C += u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    v16f acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    const int wm = wave / WGN, wn = wave % WGN;
+    v16f acc[BI][BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     const int lrow = tid >> 3, lcol = (tid & 7) * 4;
-    for (int k0 = 0; k0 < Kr; k0 += F32_BK) {
+    v4f ra[AV], rb[BV];
+    auto fetch = [&](int k0) {
         const int gk = k0 + lcol;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = lrow + 32 * i;
-            const int64_t gm = m0 + row;
-            v4f va = {0.f, 0.f, 0.f, 0.f};
-            if (gm < M && gk < Kr) va = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
-            *reinterpret_cast<v4f *>(&As[row * F32_LD + lcol]) = va;
-            const int gn = n0 + row;
-            v4f vb = {0.f, 0.f, 0.f, 0.f};
-            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
-            *reinterpret_cast<v4f *>(&Bs[row * F32_LD + lcol]) = vb;
+        for (int i = 0; i < AV; ++i) {
+            const int64_t gm = m0 + lrow + 32 * i;
+            ra[i] = v4f{0.f, 0.f, 0.f, 0.f};
+            if (gm < M && gk < Kr) ra[i] = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
+        }
+#pragma unroll
+        for (int i = 0; i < BV; ++i) {
+            const int gn = n0 + lrow + 32 * i;
+            rb[i] = v4f{0.f, 0.f, 0.f, 0.f};
+            if (gn < Nr && gk < Kr) rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) {
+            ET *dst = &As[(lrow + 32 * i) * LD + lcol];
+            if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = ra[i];
+            else split_store<NSPLIT>(dst, APART, ra[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < BV; ++i) {
+            ET *dst = &Bs[(lrow + 32 * i) * LD + lcol];
+            if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = rb[i];
+            else split_store<NSPLIT>(dst, BPART, rb[i]);
+        }
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < Kr; k0 += G_BK) {
+        const bool more = k0 + G_BK < Kr;
+        if (more) fetch(k0 + G_BK);
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int kk = 0; kk < G_BK; kk += 8) {
+                const int kofs = kk + 4 * (lane >> 5);
+                v4f a[BI], b[BJ];
+#pragma unroll
+                for (int i = 0; i < BI; ++i)
+                    a[i] = *reinterpret_cast<const v4f *>(&As[(wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
+#pragma unroll
+                for (int j = 0; j < BJ; ++j)
+                    b[j] = *reinterpret_cast<const v4f *>(&Bs[(wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < BI; ++i)
+#pragma unroll
+                        for (int j = 0; j < BJ; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < G_BK; kk += 16) {
+                const int kofs = kk + 8 * (lane >> 5);
+                bf16x8 a[BI][NSPLIT], b[BJ][NSPLIT];
+#pragma unroll
+                for (int p = 0; p < NSPLIT; ++p) {
+#pragma unroll
+                    for (int i = 0; i < BI; ++i)
+                        a[i][p] = *reinterpret_cast<const bf16x8 *>(
+                            &As[p * APART + (wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
+#pragma unroll
+                    for (int j = 0; j < BJ; ++j)
+                        b[j][p] = *reinterpret_cast<const bf16x8 *>(
+                            &Bs[p * BPART + (wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
+                }
+#pragma unroll
+                for (int i = 0; i < BI; ++i)
+#pragma unroll
+                    for (int j = 0; j < BJ; ++j) {
+                        // smallest terms first
+                        if constexpr (NSPLIT == 3) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], acc[i][j], 0, 0, 0);
+                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+                    }
+            }
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < F32_BK; kk += 8) {
-            const int kofs = kk + 4 * (lane >> 5);
-            v4f a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const v4f *>(&As[(wm * 64 + i * 32 + (lane & 31)) * F32_LD + kofs]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const v4f *>(&Bs[(wn * 64 + j * 32 + (lane & 31)) * F32_LD + kofs]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+        if (more) {
+            stash();
+            __syncthreads();
         }
-        __syncthreads();
     }
     // 32x32 accumulator layout: lane holds column lane%32 and rows
     // 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+                const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * BJ * 32 + j * 32 + (lane & 31);
                 if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
             }
 }
@@ -265,7 +421,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
     __shared__ double As[F64_BM * F64_LD];
     __shared__ double Bs[F64_BN * F64_LD];
     const int64_t u = blockIdx.y;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
     const int64_t m0 = tm * F64_BM;
     const int n0 = (int)tn * F64_BN;
@@ -279,20 +435,32 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
         for (int j = 0; j < 2; ++j)
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
     const int lrow = tid >> 2, lcol = (tid & 3) * 4;
-    for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
+    v2d ra[2], rb[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int gk = k0 + lcol + 2 * h;
             const int64_t gm = m0 + lrow;
-            v2d va = {0.0, 0.0};
-            if (gm < M && gk < Kr) va = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
-            *reinterpret_cast<v2d *>(&As[lrow * F64_LD + lcol + 2 * h]) = va;
+            ra[h] = v2d{0.0, 0.0};
+            if (gm < M && gk < Kr) ra[h] = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
             const int gn = n0 + lrow;
-            v2d vb = {0.0, 0.0};
-            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
-            *reinterpret_cast<v2d *>(&Bs[lrow * F64_LD + lcol + 2 * h]) = vb;
+            rb[h] = v2d{0.0, 0.0};
+            if (gn < Nr && gk < Kr) rb[h] = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
         }
-        __syncthreads();
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<v2d *>(&As[lrow * F64_LD + lcol + 2 * h]) = ra[h];
+            *reinterpret_cast<v2d *>(&Bs[lrow * F64_LD + lcol + 2 * h]) = rb[h];
+        }
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
+        const bool more = k0 + F64_BK < Kr;
+        if (more) fetch(k0 + F64_BK);
         const int kofs = 4 * (lane >> 4);
         v4d a[2], b[2];
 #pragma unroll
@@ -313,6 +481,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
     // 16x16 f64 accumulator layout: lane holds column lane%16 and rows lane/16 + 4*r.
 #pragma unroll
@@ -323,123 +495,6 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
                 const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
-            }
-}
-
-// ---------------------------------------------------------------------------
-// Split-BF16 compensated GEMM: each FP32 operand x is split by round-to-
-// nearest-even into bf16 parts, x = hi + lo (+ mid), and the product is
-// summed from the significant part products on the BF16 MFMA cores with FP32
-// accumulation:  NSPLIT = 2: hi*hi + hi*lo + lo*hi (3 products);
-//                NSPLIT = 3: hi*hi + hi*mid + mid*hi + hi*lo + mid*mid + lo*hi (6).
-// Operands are read as FP32 from HBM and split while being staged into LDS.
-// Same tiling as the FP32 kernel: 128 x 128 tile, k-step 32, four waves of
-// 64 x 64, v_mfma_f32_32x32x16_bf16 (a lane supplies 8 consecutive k of its
-// row / column; A and B use the same k assignment, so the sum is exact in k).
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-
-constexpr int BF_BM = 128, BF_BN = 128, BF_BK = 32, BF_LD = BF_BK + 8;
-
-template <int NSPLIT>
-__device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v) {
-    bf16x4 h, m, l;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const float x = v[e];
-        const __bf16 a = (__bf16)x;
-        const float r1 = x - (float)a;
-        const __bf16 b = (__bf16)r1;
-        h[e] = a;
-        m[e] = b;
-        if (NSPLIT == 3) l[e] = (__bf16)(r1 - (float)b);
-    }
-    *reinterpret_cast<bf16x4 *>(dst) = h;
-    *reinterpret_cast<bf16x4 *>(dst + part_stride) = m;
-    if (NSPLIT == 3) *reinterpret_cast<bf16x4 *>(dst + 2 * part_stride) = l;
-}
-
-template <int NSPLIT>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const float *__restrict__ A,
-                                                    const float *__restrict__ Bt,
-                                                    float *__restrict__ C, int64_t M, int Kr,
-                                                    int Nr, int64_t sA, int64_t sB, int64_t sC,
-                                                    int tiles_n) {
-    constexpr int PART = BF_BM * BF_LD;   // elements per split part
-    __shared__ __bf16 As[NSPLIT * PART];
-    __shared__ __bf16 Bs[NSPLIT * PART];
-    const int64_t u = blockIdx.y;
-    const int64_t tile = blockIdx.x;
-    const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
-    const int64_t m0 = tm * BF_BM;
-    const int n0 = (int)tn * BF_BN;
-    A += u * sA;
-    Bt += u * sB;
-    C += u * sC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    v16f acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    const int lrow = tid >> 3, lcol = (tid & 7) * 4;
-    for (int k0 = 0; k0 < Kr; k0 += BF_BK) {
-        const int gk = k0 + lcol;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = lrow + 32 * i;
-            const int64_t gm = m0 + row;
-            v4f va = {0.f, 0.f, 0.f, 0.f};
-            if (gm < M && gk < Kr) va = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
-            split_store<NSPLIT>(&As[row * BF_LD + lcol], PART, va);
-            const int gn = n0 + row;
-            v4f vb = {0.f, 0.f, 0.f, 0.f};
-            if (gn < Nr && gk < Kr) vb = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
-            split_store<NSPLIT>(&Bs[row * BF_LD + lcol], PART, vb);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BF_BK; kk += 16) {
-            const int kofs = kk + 8 * (lane >> 5);
-            bf16x8 a[2][NSPLIT], b[2][NSPLIT];
-#pragma unroll
-            for (int p = 0; p < NSPLIT; ++p) {
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    a[i][p] = *reinterpret_cast<const bf16x8 *>(
-                        &As[p * PART + (wm * 64 + i * 32 + (lane & 31)) * BF_LD + kofs]);
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    b[j][p] = *reinterpret_cast<const bf16x8 *>(
-                        &Bs[p * PART + (wn * 64 + j * 32 + (lane & 31)) * BF_LD + kofs]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    // smallest terms first
-                    if (NSPLIT == 3) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], acc[i][j], 0, 0, 0);
-                    }
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
-                }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int col = n0 + wn * 64 + j * 32 + (lane & 31);
                 if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
             }
 }
@@ -583,6 +638,27 @@ void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
         check_launch("permute");
         return;
     }
+    if (per < ((int64_t)1 << 31) && units <= 65535) {
+        const bool vec = elem_bytes == 8 && g.stride[g.n - 1] == 1 && g.size[g.n - 1] % 2 == 0;
+        const int64_t work = vec ? per / 2 : per;
+        const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 1023) / 1024, 65536));
+        const dim3 grid(bx, (unsigned)units);
+        if (elem_bytes == 8 && vec)
+            hipLaunchKernelGGL((k_gather32<float2, 2>), grid, dim3(256), 0, (hipStream_t)stream,
+                               (const float2 *)in, (float2 *)out, in_unit_stride, out_unit_stride, g,
+                               (uint32_t)per);
+        else if (elem_bytes == 8)
+            hipLaunchKernelGGL((k_gather32<float2, 1>), grid, dim3(256), 0, (hipStream_t)stream,
+                               (const float2 *)in, (float2 *)out, in_unit_stride, out_unit_stride, g,
+                               (uint32_t)per);
+        else
+            hipLaunchKernelGGL((k_gather32<double2, 1>), grid, dim3(256), 0, (hipStream_t)stream,
+                               (const double2 *)in, (double2 *)out, in_unit_stride, out_unit_stride, g,
+                               (uint32_t)per);
+        check_launch("gather32");
+        return;
+    }
+
     if (elem_bytes == 8)
         hipLaunchKernelGGL(k_gather<float2>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const float2 *)in, (float2 *)out, units,
@@ -626,6 +702,17 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
     check_launch("build_b");
 }
 
+template <int BI, int BJ, int WGM, int WGN>
+static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
+                       int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+    if (mode == 1)
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+    else if (mode == 2)
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+    else
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+}
+
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream) {
     // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
@@ -634,37 +721,35 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     const int c64 = mode != 0;
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
-    static_assert(BF_BM == F32_BM && BF_BN == F32_BN, "split-bf16 and FP32 tiles agree");
-    const int BM = c64 ? F32_BM : F64_BM, BN = c64 ? F32_BN : F64_BN;
+    // tile shape: 256 x 32 for N <= 16 complex, 256 x 64 for N <= 32, else 128 x 128
+    const int shape = !c64 ? 0 : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : 3));
+    const int BM = shape == 0 ? F64_BM : (shape == 3 ? 128 : 256);
+    const int BN = shape == 0 ? F64_BN : (shape == 1 ? 32 : (shape == 2 ? 64 : 128));
     const int tiles_n = (Nr + BN - 1) / BN;
     // rows per launch so that the grid stays below 2^31 blocks
     const int64_t max_tiles_m = ((int64_t)1 << 30) / tiles_n;
     const int64_t rows_per = max_tiles_m * BM;
+    const hipStream_t st = (hipStream_t)stream;
     for (int64_t u0 = 0; u0 < units; u0 += 65535) {
         const int64_t nu = std::min<int64_t>(65535, units - u0);
         for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
             const int64_t mr = std::min<int64_t>(rows_per, M - r0);
             const int64_t tiles_m = (mr + BM - 1) / BM;
             const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)nu);
-            if (mode == 2 || mode == 3) {
-                auto kern = mode == 2 ? k_gemm_bf16<2> : k_gemm_bf16<3>;
-                hipLaunchKernelGGL(kern, grid, dim3(256), 0, (hipStream_t)stream,
-                                   (const float *)A + 2 * (u0 * sA + r0 * K),
-                                   (const float *)Bt + 4 * u0 * sB,
-                                   (float *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
-                                   2 * sC, tiles_n);
-            } else if (c64)
-                hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, (hipStream_t)stream,
-                                   (const float *)A + 2 * (u0 * sA + r0 * K),
-                                   (const float *)Bt + 4 * u0 * sB,
-                                   (float *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
-                                   2 * sC, tiles_n);
-            else
-                hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, (hipStream_t)stream,
+            if (c64) {
+                const float *a = (const float *)A + 2 * (u0 * sA + r0 * K);
+                const float *b = (const float *)Bt + 4 * u0 * sB;
+                float *c = (float *)C + 2 * (u0 * sC + r0 * N);
+                if (shape == 1) launch_c64<2, 1, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
+                else if (shape == 2) launch_c64<2, 2, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
+                else launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
+            } else {
+                hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st,
                                    (const double *)A + 2 * (u0 * sA + r0 * K),
                                    (const double *)Bt + 4 * u0 * sB,
                                    (double *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
                                    2 * sC, tiles_n);
+            }
             check_launch("gemm");
         }
     }
