@@ -9,6 +9,7 @@
 #include <limits>
 #include <numeric>
 #include <queue>
+#include <random>
 #include <unordered_set>
 
 #include "internal.h"
@@ -834,8 +835,74 @@ static Sliced cuts_for_order(const Plan &p, const std::vector<int> &order, std::
     return r;
 }
 
-// Cut choice ("chosen empirically ... where the lattice is the thinnest") is
-// automated: plan a path on the whole network, cut against that path, then
+// Cut search by simulated annealing.  The paper cuts first and then plans
+// the path of the sliced network; the choice of cut set dominates the cost
+// when no single bond stays open across the expensive part of a linear path.
+// State: a set of cut bonds.  Evaluation: greedy path of the network with
+// those bonds removed, completed by cuts_for_order until every intermediate
+// fits the limit; cost = slices x score.  Moves add, remove or replace one
+// bond; acceptance is Metropolis on log(cost) with a linearly falling
+// temperature.  Deterministic for a given seed.
+static Sliced anneal_cuts(const Plan &p, double limit, int iters, uint64_t seed,
+                          std::vector<int> *order_out) {
+    const Circuit &c = p.circ;
+    const auto &E = c.g.edges;
+    std::vector<int> cand;
+    for (size_t e = 0; e < E.size(); ++e)
+        if (p.bond_overlap[e] > 1) cand.push_back((int)e);
+    std::mt19937_64 rng(seed);
+    auto eval = [&](const std::vector<int> &cuts, std::vector<int> *ord) {
+        PathResult r = path_search(c.n, E, dims_with_cuts(p, cuts), TNS_PATH_GREEDY, 0, true, 0);
+        Sliced sl = cuts_for_order(p, r.order, cuts, limit);
+        if (sl.peak > limit || sl.slices > 1e12 || (int)sl.cuts.size() > kMaxCuts)
+            sl.total = std::numeric_limits<double>::infinity();
+        if (ord) *ord = r.order;
+        return sl;
+    };
+    std::vector<int> cur, cur_order;
+    Sliced cs = eval(cur, &cur_order);
+    Sliced best = cs;
+    std::vector<int> best_order = cur_order;
+    if (cand.empty()) {
+        if (order_out) *order_out = best_order;
+        return best;
+    }
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    for (int it = 0; it < iters; ++it) {
+        const double temp = 2.0 * (1.0 - (double)it / iters) + 1e-3;
+        std::vector<int> prop = cur;
+        const double r = U(rng);
+        const int pick = cand[rng() % cand.size()];
+        if (r < 0.4 || prop.empty()) {
+            if (std::find(prop.begin(), prop.end(), pick) == prop.end()) prop.push_back(pick);
+        } else if (r < 0.7) {
+            prop.erase(prop.begin() + (long)(rng() % prop.size()));
+        } else {
+            prop[rng() % prop.size()] = pick;
+            std::sort(prop.begin(), prop.end());
+            prop.erase(std::unique(prop.begin(), prop.end()), prop.end());
+        }
+        std::vector<int> ord;
+        Sliced ps = eval(prop, &ord);
+        bool accept = ps.total < cs.total;
+        if (!accept && std::isfinite(ps.total) && std::isfinite(cs.total))
+            accept = U(rng) < std::exp(-(std::log(ps.total) - std::log(cs.total)) / temp);
+        if (!std::isfinite(cs.total) && std::isfinite(ps.total)) accept = true;
+        if (accept) {
+            cur = prop;
+            cs = ps;
+            if (ps.total < best.total) {
+                best = ps;
+                best_order = ord;
+            }
+        }
+    }
+    if (order_out) *order_out = best_order;
+    return best;
+}
+
+// The paper picks its cuts by hand, at narrow parts of the lattice; here the
+// choice is automated: plan a path on the whole network, cut against that path, then
 // also re-plan the path on the sliced network as the paper does for its
 // sub-networks, and keep whichever has the least total cost within the limit.
 static void choose_cuts_and_path(Plan &p) {
@@ -889,6 +956,20 @@ static void choose_cuts_and_path(Plan &p) {
             Sliced s2 = cuts_for_order(p, r2.order, s.cuts, limit);
             consider(r2, s2);
         }
+        if (!best.cuts.empty() || !std::isfinite(best.total)) {
+            // cut search, then the requested path search on the sliced network
+            std::vector<int> order;
+            Sliced sa = anneal_cuts(p, limit, 2000, 0x5eed5eedULL + p.split, &order);
+            if (std::isfinite(sa.total)) {
+                PathResult r;
+                r.order = order;
+                consider(r, sa);
+                if (p.opts.path_mode != TNS_PATH_GREEDY) {
+                    PathResult r3 = search(dims_with_cuts(p, sa.cuts), p.opts.path_mode);
+                    consider(r3, cuts_for_order(p, r3.order, sa.cuts, limit));
+                }
+            }
+        }
         if (!std::isfinite(best.total))
             fail(TNS_E_OUT_OF_MEMORY, "no cut set brings the largest intermediate under the limit");
         p.cuts = best.cuts;
@@ -924,19 +1005,38 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
     if (opts.split_cycle >= 0) {
         p.split = opts.split_cycle;
     } else {
-        // choose the split with the least sliced cost of a greedy path
+        // choose the split with the least sliced cost of a greedy path; splits
+        // whose network needs cuts get an annealed cut search, but only when
+        // their unsliced score could still beat the best total found
         const double limit = (double)(opts.max_intermediate_elems ? opts.max_intermediate_elems
                                                                    : (1ULL << 32));
-        double best = std::numeric_limits<double>::infinity();
-        int bk = 0;
+        const double inf = std::numeric_limits<double>::infinity();
+        std::vector<double> total(depth + 1, inf), score0(depth + 1, inf);
+        std::vector<char> needs_cuts(depth + 1, 0);
         for (int k = 0; k <= depth; ++k) {
             evolve_both(p, k);
             std::vector<double> d(p.bond_overlap.begin(), p.bond_overlap.end());
             PathResult r = path_search(c.n, c.g.edges, d, TNS_PATH_GREEDY, 0, true, 0);
             Sliced sl = cuts_for_order(p, r.order, {}, limit);
-            double t = sl.peak <= limit ? sl.total : std::numeric_limits<double>::infinity();
-            if (t < best) { best = t; bk = k; }
+            score0[k] = r.score;
+            total[k] = sl.peak <= limit ? sl.total : inf;
+            needs_cuts[k] = !sl.cuts.empty();
         }
+        double best = *std::min_element(total.begin(), total.end());
+        std::vector<int> byscore(depth + 1);
+        std::iota(byscore.begin(), byscore.end(), 0);
+        std::sort(byscore.begin(), byscore.end(), [&](int a2, int b2) { return score0[a2] < score0[b2]; });
+        for (int k : byscore) {
+            if (!needs_cuts[k] || opts.n_cuts >= 0 || !(score0[k] < best)) continue;
+            evolve_both(p, k);
+            p.split = k;
+            Sliced sa = anneal_cuts(p, limit, 600, 0x5eed5eedULL + k, nullptr);
+            total[k] = std::min(total[k], sa.total);
+            best = std::min(best, total[k]);
+        }
+        int bk = 0;
+        for (int k = 0; k <= depth; ++k)
+            if (total[k] < total[bk]) bk = k;
         p.split = bk;
     }
     evolve_both(p, p.split);
