@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-d12", action="store_true", help="skip the 53-qubit depth-12 slice timing")
+    ap.add_argument("--d12-slices", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slice "
@@ -171,18 +173,48 @@ def main():
                                 "f_ovl": float(abs(np.vdot(ref, test)) ** 2 / (np.vdot(ref, ref).real * np.vdot(test, test).real))}
         print(f"[bench] {other} done", file=sys.stderr, flush=True)
 
-    # 53-qubit depth-12 plan from a planning-only context: cost and extrapolation
-    try:
-        pctx = T.Context(-1)
-        c53, _ = config("diag53_d12")
-        i53 = pctx.plan(c53, precision="c64", max_search_states=1000000).info()
-        rate = gemm_tflops * 1e12 if gemm_tflops > 0 else tflops * 1e12
-        extra["diag53_d12_plan"] = {"flops_per_amp": i53.flops_per_amp, "n_slices": int(i53.n_slices),
-                                    "split": int(i53.split_cycle), "peak_elems": int(i53.peak_elems),
-                                    "est_s_per_amp_at_measured_gemm_rate": i53.flops_per_amp / rate if rate else None}
-        pctx.close()
-    except Exception as e:  # planning failure is reported, not fatal
-        extra["diag53_d12_plan"] = {"error": str(e)}
+    # 53 qubits at depth 12: one amplitude is ~1e17 flops, so a few of its
+    # slices are timed (partial sums over a slice range) and the full
+    # amplitude is extrapolated; c64, split-BF16 and c128 partial sums are
+    # compared with each other.
+    if not args.no_d12:
+        try:
+            c53, b53 = config("diag53_d12", n_bits=1)
+            t = time.perf_counter()
+            p64 = ctx.plan(c53, precision="c64")
+            t_plan53 = time.perf_counter() - t
+            i53 = p64.info()
+            same = dict(split_cycle=int(i53.split_cycle), path=i53.path.tolist(),
+                        cuts=i53.cut_edges.tolist())
+            ns = int(i53.n_slices)
+            nt = min(ns, args.d12_slices)
+            res = {"flops_per_amp": i53.flops_per_amp, "n_slices": ns, "split": int(i53.split_cycle),
+                   "peak_elems": int(i53.peak_elems), "plan_s": round(t_plan53, 2), "slices_timed": nt}
+            parts = {}
+            for prec, plan53 in (("c64", p64), ("c64_bf16x3", None), ("c128", None)):
+                if plan53 is None:
+                    plan53 = ctx.plan(c53, precision=prec, **same)
+                ctx.amplitudes(plan53, b53, slices=(0, 1))          # warm-up: one slice
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                a, st = ctx.amplitudes(plan53, b53, slices=(0, nt), stats=True)
+                dt53 = time.perf_counter() - t
+                parts[prec] = a
+                fl = i53.flops_per_amp * nt / ns
+                res[prec] = {"s_per_slice": round(dt53 / nt, 3), "est_s_per_amp": round(dt53 / nt * ns, 1),
+                             "tflops": round(fl / dt53 / 1e12, 2),
+                             "gemm_tflops": round(st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12, 2)
+                             if st["ms_gemm"] else None}
+                if plan53 is not p64:
+                    plan53.close()
+                print(f"[bench] diag53_d12 {prec}: {dt53 / nt:.2f} s/slice", file=sys.stderr, flush=True)
+            ref = parts["c128"]
+            for prec in ("c64", "c64_bf16x3"):
+                res[prec]["partial_rel_err_vs_c128"] = float(abs(parts[prec][0] - ref[0]) / abs(ref[0]))
+            extra["diag53_d12"] = res
+            p64.close()
+        except Exception as e:  # a failure here is reported, not fatal
+            extra["diag53_d12"] = {"error": str(e)}
 
     if not args.no_serving:
         extra["serving"] = serving_run(T, ctx)

@@ -218,6 +218,17 @@ tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                           const uint8_t *bits, double *amps, void *hip_stream,
                           tns_stats *stats);
 
+/* Partial amplitudes over the slices [slice_begin, slice_end) of the plan's
+ * cut bonds: amps[b] = sum over those slices of the sub-network scalars
+ * (overlap paragraph: every slice of the cut network yields one scalar and
+ * the scalars add up to the amplitude).  Partial sums over disjoint ranges
+ * covering [0, n_slices) add up to the amplitudes of tns_amplitudes, so the
+ * slices of one amplitude can be split over calls, streams or devices.
+ * 0 <= slice_begin < slice_end <= n_slices, else TNS_E_INVALID_ARG. */
+tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n,
+                                 const uint8_t *bits, int64_t slice_begin, int64_t slice_end,
+                                 double *amps, void *hip_stream, tns_stats *stats);
+
 /* --- serving ---------------------------------------------------------- */
 
 /* Asynchronous request: queued, admitted by memory, and executed by the

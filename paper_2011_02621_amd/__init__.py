@@ -25,6 +25,7 @@ PATH_MODE = {"greedy": 0, "algorithm1": 1}
 
 EXPORTED = ["tns_init", "tns_set_allocator", "tns_finalize", "tns_plan_opts_default",
             "tns_plan_create", "tns_plan_info_get", "tns_plan_destroy", "tns_amplitudes",
+            "tns_amplitudes_sliced",
             "tns_submit", "tns_poll", "tns_wait", "tns_cancel", "tns_request_free",
             "tns_request_latency", "tns_path_search", "tns_last_error", "tns_version"]
 
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH):
         "tns_plan_info_get": ([vp, ctypes.POINTER(_PlanInfo)], i32),
         "tns_plan_destroy": ([vp], i32),
         "tns_amplitudes": ([vp, vp, i64, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
+        "tns_amplitudes_sliced": ([vp, vp, i64, vp, i64, i64, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_submit": ([vp, vp, i64, vp, vp, ctypes.POINTER(vp)], i32),
         "tns_poll": ([vp, ctypes.POINTER(ctypes.c_int)], i32),
         "tns_wait": ([vp], i32),
@@ -328,14 +330,22 @@ class Context:
         return Plan(self, h, [])
 
     def amplitudes(self, plan: Plan, bits: np.ndarray, stream: Optional[int] = None,
-                   stats: bool = False):
+                   stats: bool = False, slices: Optional[tuple] = None):
+        """Amplitudes of the rows of ``bits``; with ``slices=(begin, end)`` the
+        partial sums over that range of slices."""
         bits = np.ascontiguousarray(bits, np.uint8)
         nq = plan.info().n_qubits if bits.ndim == 1 else bits.shape[1]
         bits = bits.reshape(-1, nq)
         amps = np.zeros((bits.shape[0], 2), np.float64)
         st = _Stats()
-        _check(load_library().tns_amplitudes(self._h, plan._h, bits.shape[0], bits.ctypes.data,
-                                             amps.ctypes.data, stream, ctypes.byref(st)))
+        lib = load_library()
+        if slices is None:
+            _check(lib.tns_amplitudes(self._h, plan._h, bits.shape[0], bits.ctypes.data,
+                                      amps.ctypes.data, stream, ctypes.byref(st)))
+        else:
+            _check(lib.tns_amplitudes_sliced(self._h, plan._h, bits.shape[0], bits.ctypes.data,
+                                             int(slices[0]), int(slices[1]), amps.ctypes.data,
+                                             stream, ctypes.byref(st)))
         out = amps.view(np.complex128).reshape(-1)
         if stats:
             return out, {f: getattr(st, f) for f, _ in _Stats._fields_}

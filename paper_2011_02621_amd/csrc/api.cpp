@@ -377,8 +377,9 @@ tns_status tns_plan_destroy(tns_plan *p) {
     });
 }
 
-tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
-                          double *amps, void *hip_stream, tns_stats *stats) {
+static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
+                                  int64_t slice_begin, int64_t slice_end, double *amps,
+                                  void *hip_stream, tns_stats *stats) {
     return guard([&] {
         auto t0 = clk::now();
         if (!ctx || !plan) fail(TNS_E_INVALID_ARG, "ctx or plan is NULL");
@@ -386,6 +387,9 @@ tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const u
         if (n > 0 && (!bits || !amps)) fail(TNS_E_INVALID_ARG, "bits or amps is NULL");
         if (ctx->device < 0) fail(TNS_E_NO_DEVICE, "planning-only context cannot compute amplitudes");
         if (!plan->on_device || plan->ctx != ctx) fail(TNS_E_INVALID_ARG, "plan was not created on this context");
+        if (slice_end < 0) slice_end = plan->n_slices;
+        if (slice_begin < 0 || slice_begin >= slice_end || slice_end > plan->n_slices)
+            fail(TNS_E_INVALID_ARG, "slice range must satisfy 0 <= begin < end <= n_slices");
         for (int64_t i = 0; i < n * plan->circ.n; ++i)
             if (bits[i] > 1) fail(TNS_E_INVALID_ARG, "bits must be 0 or 1");
         RunStats rs;
@@ -394,7 +398,8 @@ tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const u
             std::lock_guard<std::mutex> lk(ctx->mu);
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
             void *st = hip_stream ? hip_stream : ctx->stream;
-            run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, ctx->budget);
+            run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, ctx->budget, slice_begin,
+                           slice_end);
         }
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
@@ -415,6 +420,21 @@ tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const u
             stats->ms_small = rs.ms_small;
         }
     });
+}
+
+tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
+                          double *amps, void *hip_stream, tns_stats *stats) {
+    return amplitudes_impl(ctx, plan, n, bits, 0, -1, amps, hip_stream, stats);
+}
+
+tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
+                                 int64_t slice_begin, int64_t slice_end, double *amps,
+                                 void *hip_stream, tns_stats *stats) {
+    if (slice_end < 0) {
+        set_last_error("slice_end must be >= 0");
+        return TNS_E_INVALID_ARG;
+    }
+    return amplitudes_impl(ctx, plan, n, bits, slice_begin, slice_end, amps, hip_stream, stats);
 }
 
 tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,

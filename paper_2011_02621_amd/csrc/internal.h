@@ -271,7 +271,8 @@ struct RunStats {
 // most `budget` bytes of workspace beyond the plan's resident tensors.
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
-                    const volatile int *cancel, uint64_t budget);
+                    const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
+                    int64_t slice_end = -1);
 int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
 
 // ----------------------------------------------------------------------------
@@ -300,10 +301,10 @@ void merge(const double *ket, const double *bra, void *out, int64_t nb, int64_t 
 void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
             int64_t out_unit_stride, const Gather &g, int elem_bytes, void *stream);
 void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
-                 int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
+                 int64_t slice0, int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
                  const Gather &g, int elem_bytes, void *stream);
 void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
-             int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
+             int64_t slice0, int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream);
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream);

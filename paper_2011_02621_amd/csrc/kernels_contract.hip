@@ -156,10 +156,11 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const E *__restrict__ in,
     }
 }
 
-// unit u of this launch is global unit ug = u0 + u = bitstring * n_slices + slice
+// unit u of this launch is global unit ug = u0 + u = bitstring * n_slices + j,
+// computing slice slice0 + j
 template <typename E>
 __global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, int64_t units,
-                              int64_t u0, int64_t n_slices, int64_t site_stride,
+                              int64_t u0, int64_t n_slices, int64_t slice0, int64_t site_stride,
                               SliceMap sm, int64_t out_us, Gather g,
                               int64_t per) {
     const int64_t total = per * units;
@@ -167,7 +168,7 @@ __global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, i
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t u = t / per, i = t - u * per;
         const int64_t ug = u0 + u;
-        const int64_t b = ug / n_slices, s = ug - b * n_slices;
+        const int64_t b = ug / n_slices, s = slice0 + ug - b * n_slices;
         const int64_t base = b * site_stride + slice_offset(sm, s);
         out[u * out_us + i] = site[base + gather_offset(g, i)];
     }
@@ -179,7 +180,7 @@ __global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, i
 //   Bt[2n][2k] = Re b, Bt[2n][2k+1] = -Im b, Bt[2n+1][2k] = Im b, Bt[2n+1][2k+1] = Re b.
 template <typename R>
 __global__ void k_build_b(const R *__restrict__ site, R *__restrict__ out, int64_t units,
-                          int64_t u0, int64_t n_slices, int64_t site_stride,
+                          int64_t u0, int64_t n_slices, int64_t slice0, int64_t site_stride,
                           SliceMap sm, Gather g, int64_t K, int64_t N,
                           int embed) {
     const int64_t per = K * N;
@@ -188,7 +189,7 @@ __global__ void k_build_b(const R *__restrict__ site, R *__restrict__ out, int64
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t u = t / per, i = t - u * per;
         const int64_t ug = u0 + u;
-        const int64_t b = ug / n_slices, s = ug - b * n_slices;
+        const int64_t b = ug / n_slices, s = slice0 + ug - b * n_slices;
         const int64_t src = b * site_stride + slice_offset(sm, s) + gather_offset(g, i);
         const R re = site[2 * src], im = site[2 * src + 1];
         if (!embed) {
@@ -671,7 +672,7 @@ void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
 }
 
 void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
-                 int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
+                 int64_t slice0, int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
                  const Gather &g, int elem_bytes, void *stream) {
     int64_t per = 1;
     for (int a = 0; a < g.n; ++a) per *= g.size[a];
@@ -679,26 +680,26 @@ void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t
     if (elem_bytes == 8)
         hipLaunchKernelGGL(k_gather_site<float2>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const float2 *)site, (float2 *)out, units, u0,
-                           n_slices, site_stride, sm, out_unit_stride, g, per);
+                           n_slices, slice0, site_stride, sm, out_unit_stride, g, per);
     else
         hipLaunchKernelGGL(k_gather_site<double2>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const double2 *)site, (double2 *)out, units, u0,
-                           n_slices, site_stride, sm, out_unit_stride, g, per);
+                           n_slices, slice0, site_stride, sm, out_unit_stride, g, per);
     check_launch("gather_site");
 }
 
 void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
-             int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
+             int64_t slice0, int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream) {
     const int64_t total = K * N * units;
     if (c64)
         hipLaunchKernelGGL(k_build_b<float>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const float *)site, (float *)out, units, u0,
-                           n_slices, site_stride, sm, g, K, N, embed);
+                           n_slices, slice0, site_stride, sm, g, K, N, embed);
     else
         hipLaunchKernelGGL(k_build_b<double>, dim3(grid_for(total, 256)), dim3(256), 0,
                            (hipStream_t)stream, (const double *)site, (double *)out, units, u0,
-                           n_slices, site_stride, sm, g, K, N, embed);
+                           n_slices, slice0, site_stride, sm, g, K, N, embed);
     check_launch("build_b");
 }
 

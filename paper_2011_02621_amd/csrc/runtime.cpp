@@ -234,8 +234,11 @@ struct Timer {
 
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
-                    const volatile int *cancel, uint64_t budget) {
+                    const volatile int *cancel, uint64_t budget, int64_t slice_begin,
+                    int64_t slice_end) {
     const Circuit &c = p.circ;
+    if (slice_end < 0) slice_end = p.n_slices;
+    const int64_t n_sl = slice_end - slice_begin;   // slices computed per bitstring
     const bool c64 = p.precision != TNS_C128;
     const int elem = c64 ? 8 : 16;
     const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget));
@@ -297,7 +300,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
 
         // ---- contraction of every (bitstring, slice) unit along the path
         Timer tc(stream, timing);
-        const int64_t units = nb * p.n_slices;
+        const int64_t units = nb * n_sl;
         double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * 16, stream);
         const uint64_t used = ws.bytes;
         const uint64_t left = budget > used ? budget - used : 0;
@@ -329,7 +332,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
             if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
             const int64_t g = std::min(G, units - ug0);
             const Step &s0 = p.steps[0];
-            launch::gather_site(site_ptr[s0.site], X, g, ug0, p.n_slices, p.site_elems[s0.site],
+            launch::gather_site(site_ptr[s0.site], X, g, ug0, n_sl, slice_begin, p.site_elems[s0.site],
                                 p.slice_map[s0.site],
                                 peak, s0.bgather, elem, stream);
             char *cur = X;
@@ -348,7 +351,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     st.launches += 1;
                 }
                 char *dst = (src == X) ? Y : X;
-                launch::build_b(site_ptr[s.site], Bb, g, ug0, p.n_slices, p.site_elems[s.site],
+                launch::build_b(site_ptr[s.site], Bb, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
                                 p.slice_map[s.site],
                                 s.bgather, s.K, s.N, c64 ? 1 : 0, s.kernel == 0 ? 1 : 0, stream);
                 const double mkn = (double)s.M * s.K * s.N * g;
@@ -366,7 +369,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 cur = dst;
             }
         }
-        launch::slice_sum(partial, amps_dev + 2 * b0, nb, p.n_slices, stream);
+        launch::slice_sum(partial, amps_dev + 2 * b0, nb, n_sl, stream);
         st.launches += 1;
         st.ms_contract += tc.stop();
         for (Ev &e : evs) {
@@ -379,7 +382,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
             (void)hipEventDestroy(e.b);
         }
         st.units += units;
-        st.flops += p.flops_per_amp * nb;
+        st.flops += p.flops_per_amp * nb * ((double)n_sl / (double)p.n_slices);
     }
     hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * 16, hipMemcpyDeviceToHost,
                              (hipStream_t)stream), "amplitude download");

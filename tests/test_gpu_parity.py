@@ -93,6 +93,19 @@ def test_grid3x4_paths_and_cuts_agree(ctx, small):
         assert compare(ref, got, c.n)["rel_l2"] <= 1e-12, v
 
 
+def test_slice_ranges_add_up(ctx, small):
+    c, bits, ref = small
+    p = ctx.plan(c, split_cycle=4, precision="c128", cuts=[2, 9])
+    ns = p.info().n_slices
+    say("grid3x4_d8 slice ranges of", ns)
+    full = ctx.amplitudes(p, bits)
+    parts = [ctx.amplitudes(p, bits, slices=r) for r in ((0, 1), (1, 100), (100, ns))]
+    assert compare(full, sum(parts), c.n)["rel_l2"] <= 1e-13
+    check(ref, full, c.n, "c128")
+    with pytest.raises(T.TnsError):
+        ctx.amplitudes(p, bits, slices=(5, 5))
+
+
 def test_no_final_layer(ctx):
     c, bits = config("grid3x4_d8", final_layer=False)
     ref = sv.amplitudes(c, bits)
