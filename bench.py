@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-d12", action="store_true", help="skip the 53-qubit depth-12 slice timing")
     ap.add_argument("--d12-slices", type=int, default=2)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB of a plain device copy run first (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slice "
@@ -97,8 +99,16 @@ def main():
 
     import torch
     import paper_2011_02621_amd as T
-    from circuits import config
+    from circuits import config, random_circuit, diagonal53, bitstrings
 
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling HBM byte counters
+        nbytes = args.copy_calibration << 20
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     circ, bits = config(args.workload, n_bits=args.bits or None)
     n_q = circ.n
     ctx = T.Context(0)
@@ -215,6 +225,33 @@ def main():
             p64.close()
         except Exception as e:  # a failure here is reported, not fatal
             extra["diag53_d12"] = {"error": str(e)}
+
+    # 53 qubits at depth 10 (the deepest column of the paper's single-amplitude
+    # table): full amplitudes, c64 and c128
+    if not args.no_d12:
+        try:
+            c10 = random_circuit(diagonal53(), 10, 3)
+            b10 = bitstrings(53, 64, 103)
+            res = {}
+            amps10 = {}
+            for prec in ("c64", "c128"):
+                p10 = ctx.plan(c10, precision=prec)
+                ctx.amplitudes(p10, b10[:2])
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                amps10[prec] = ctx.amplitudes(p10, b10)
+                dt10 = time.perf_counter() - t
+                i10 = p10.info()
+                res[prec] = {"amps_per_s": round(len(b10) / dt10, 2),
+                             "tflops": round(i10.flops_per_amp * len(b10) / dt10 / 1e12, 2)}
+                res["flops_per_amp"] = i10.flops_per_amp
+                p10.close()
+            res["c64_rel_l2_vs_c128"] = rel_l2(amps10["c128"], amps10["c64"])
+            res["bitstrings"] = len(b10)
+            extra["diag53_d10"] = res
+            print(f"[bench] diag53_d10 done", file=sys.stderr, flush=True)
+        except Exception as e:
+            extra["diag53_d10"] = {"error": str(e)}
 
     if not args.no_serving:
         extra["serving"] = serving_run(T, ctx)
