@@ -122,8 +122,12 @@ typedef struct {
                                   when reporting numerical ranks; 0 = 1e-12 */
     int64_t max_search_states; /* Algorithm 1 pop budget; 0 = 4,000,000 */
     tns_precision precision;
-    int32_t n_open;            /* reserved, must be 0 */
-    const int32_t *open_qubits;/* reserved, must be NULL */
+    int32_t n_open;            /* 0..20 qubits whose output bit is left open */
+    const int32_t *open_qubits;/* [n_open] distinct qubits, or NULL when n_open = 0.
+                                  The bra's bit of each open qubit stays a free leg, so
+                                  one contraction yields the 2^n_open amplitudes of all
+                                  bitstrings that agree outside these qubits (the rest
+                                  of the network, and its contraction, is shared). */
 } tns_plan_opts;
 
 /* Description of a plan.  Pointers refer to plan-owned memory, valid until
@@ -156,6 +160,8 @@ typedef struct {
     double fidelity;                /* Eq. (9) with the paper's Sycamore error rates */
     double n_samples;               /* (3 / fidelity)^2 */
     tns_precision precision;
+    int32_t n_open;                 /* open qubits; each input bitstring yields 2^n_open amplitudes */
+    const int32_t *open_qubits;     /* [n_open] */
 } tns_plan_info;
 
 typedef struct {
@@ -213,7 +219,10 @@ tns_status tns_plan_destroy(tns_plan *plan);
 /* amps[2*b], amps[2*b+1] = <s_b|U|0...0> for b < n.  bits and amps are host
  * arrays; amps is written only on TNS_OK.  hip_stream = NULL uses the
  * context's stream.  stats may be NULL.  Blocks until the results are on the
- * host. */
+ * host.  With open qubits amps holds [n][2^n_open] complex values: entry
+ * (b, x) is the amplitude of s_b with its open bits replaced by the bits of x,
+ * the first open qubit being the most significant bit of x; the bits given
+ * for open qubits are ignored. */
 tns_status tns_amplitudes(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                           const uint8_t *bits, double *amps, void *hip_stream,
                           tns_stats *stats);

@@ -83,7 +83,8 @@ class _PlanInfo(ctypes.Structure):
                 ("n_fused_bra", ctypes.c_int32), ("search_complete", ctypes.c_int32),
                 ("search_states", ctypes.c_int64), ("max_rank_used", ctypes.c_int32),
                 ("fidelity", ctypes.c_double), ("n_samples", ctypes.c_double),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("n_open", ctypes.c_int32),
+                ("open_qubits", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _Stats(ctypes.Structure):
@@ -190,6 +191,7 @@ class PlanInfo:
     fidelity: float
     n_samples: float
     precision: int
+    open_qubits: np.ndarray
 
 
 def _arr(ptr, n, dtype):
@@ -201,6 +203,9 @@ def _arr(ptr, n, dtype):
 class Plan:
     def __init__(self, ctx: "Context", handle, keep):
         self.ctx, self._h, self._keep = ctx, handle, keep
+        inf = self.info()
+        self.n_qubits = inf.n_qubits
+        self.n_open = len(inf.open_qubits)
 
     def info(self) -> PlanInfo:
         inf = _PlanInfo()
@@ -216,7 +221,7 @@ class Plan:
             inf.gemm_bytes_per_amp, inf.permute_bytes_per_amp, inf.path_score, inf.peak_elems,
             inf.device_bytes_resident, inf.device_bytes_per_unit, inf.n_fused_ket,
             inf.n_fused_bra, bool(inf.search_complete), inf.search_states, inf.max_rank_used,
-            inf.fidelity, inf.n_samples, inf.precision)
+            inf.fidelity, inf.n_samples, inf.precision, _arr(inf.open_qubits, inf.n_open, np.int32))
 
     def close(self):
         if self._h:
@@ -299,7 +304,7 @@ class Context:
              path_mode: str = "algorithm1", max_rank: int = 0, path_assumptions: bool = True,
              cuts: Optional[Sequence[int]] = None, max_intermediate_elems: int = 1 << 32,
              precision: str = "c128", max_search_states: int = 0,
-             svd_rel_cutoff: float = 1e-12) -> Plan:
+             svd_rel_cutoff: float = 1e-12, open_qubits: Optional[Sequence[int]] = None) -> Plan:
         lib = load_library()
         n, edges, gates = _circuit_arrays(circ)
         desc = _CircuitDesc(n, edges.shape[0], edges.ctypes.data, gates.shape[0], gates.ctypes.data)
@@ -325,6 +330,11 @@ class Context:
         o.svd_rel_cutoff = float(svd_rel_cutoff)
         o.max_search_states = int(max_search_states)
         o.precision = PRECISION[precision]
+        if open_qubits:
+            oq = np.ascontiguousarray(open_qubits, np.int32)
+            keep.append(oq)
+            o.n_open = len(oq)
+            o.open_qubits = oq.ctypes.data
         h = ctypes.c_void_p()
         _check(lib.tns_plan_create(self._h, ctypes.byref(desc), ctypes.byref(o), ctypes.byref(h)))
         return Plan(self, h, [])
@@ -333,10 +343,9 @@ class Context:
                    stats: bool = False, slices: Optional[tuple] = None):
         """Amplitudes of the rows of ``bits``; with ``slices=(begin, end)`` the
         partial sums over that range of slices."""
-        bits = np.ascontiguousarray(bits, np.uint8)
-        nq = plan.info().n_qubits if bits.ndim == 1 else bits.shape[1]
-        bits = bits.reshape(-1, nq)
-        amps = np.zeros((bits.shape[0], 2), np.float64)
+        bits = np.ascontiguousarray(bits, np.uint8).reshape(-1, plan.n_qubits)
+        per = 1 << plan.n_open
+        amps = np.zeros((bits.shape[0] * per, 2), np.float64)
         st = _Stats()
         lib = load_library()
         if slices is None:
@@ -347,13 +356,15 @@ class Context:
                                              int(slices[0]), int(slices[1]), amps.ctypes.data,
                                              stream, ctypes.byref(st)))
         out = amps.view(np.complex128).reshape(-1)
+        if plan.n_open:
+            out = out.reshape(bits.shape[0], per)
         if stats:
             return out, {f: getattr(st, f) for f, _ in _Stats._fields_}
         return out
 
     def submit(self, plan: Plan, bits: np.ndarray) -> Request:
-        bits = np.ascontiguousarray(bits, np.uint8).reshape(-1, plan.info().n_qubits)
-        amps = np.zeros((bits.shape[0], 2), np.float64)
+        bits = np.ascontiguousarray(bits, np.uint8).reshape(-1, plan.n_qubits)
+        amps = np.zeros((bits.shape[0] << plan.n_open, 2), np.float64)
         h = ctypes.c_void_p()
         _check(load_library().tns_submit(self._h, plan._h, bits.shape[0], bits.ctypes.data,
                                          amps.ctypes.data, ctypes.byref(h)))

@@ -177,7 +177,8 @@ struct Server {
             std::string err;
             RunStats rs;
             try {
-                run_amplitudes(ctx, *r->plan, b1 - b0, r->bits + b0 * r->plan->circ.n, r->amps + 2 * b0,
+                run_amplitudes(ctx, *r->plan, b1 - b0, r->bits + b0 * r->plan->circ.n,
+                               r->amps + 2 * b0 * r->plan->out_per_unit,
                                streams[wi], ws[wi], rs, &r->cancel, worker_budget);
             } catch (const Error &e) {
                 st = e.code;
@@ -314,6 +315,7 @@ tns_status tns_plan_create(tns_ctx *ctx, const tns_circuit_desc *desc, const tns
         if (o.n_cuts < -1) fail(TNS_E_INVALID_ARG, "n_cuts must be >= -1");
         Circuit c;
         validate_and_build(desc, c);
+        add_open_legs(c, o);
         if (o.split_cycle > c.max_cycle + 1) fail(TNS_E_INVALID_ARG, "split_cycle beyond the last cycle");
         std::unique_ptr<tns_plan> p(new tns_plan());
         plan_host(c, o, *p);
@@ -365,6 +367,8 @@ tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
         o->fidelity = p->fidelity;
         o->n_samples = p->n_samples;
         o->precision = (tns_precision)p->precision;
+        o->n_open = p->circ.n_open;
+        o->open_qubits = p->circ.open_qubits.data();
     });
 }
 

@@ -130,12 +130,16 @@ struct Plan;
 
 struct Circuit {
     int n = 0;
-    Graph g;
+    Graph g;                       // real couplers first, then one dangling leg per open qubit
     std::vector<tns_gate> gates;
     int max_cycle = 0;
+    int n_real_edges = 0;
+    int n_open = 0;
+    std::vector<int> open_qubits;  // the bra's output bit of these qubits stays an open leg
 };
 
 void validate_and_build(const tns_circuit_desc *desc, Circuit &c);
+void add_open_legs(Circuit &c, const tns_plan_opts &opts);
 int operator_schmidt_rank(const double *m32);
 
 struct PathResult {
@@ -203,6 +207,8 @@ struct Plan {
 
     // per-site slice offsets of the cut bonds
     std::vector<SliceMap> slice_map;
+    int64_t out_per_unit = 1;            // 2^(open qubits): values per (bitstring, slice)
+    Gather final_perm{};                 // open legs of the last tensor -> output order
 
     // info arrays exposed through tns_plan_info
     std::vector<int64_t> info_m, info_k, info_n;
@@ -285,7 +291,7 @@ void fuse_split(const double *mats, const int32_t *chain, const int32_t *chain_o
                 const int32_t *bra_chain, double *ket_vec, double *bra_mat, void *stream);
 void init_ket(const double *ket_vec, int q, double *site, void *stream);
 void init_bra(const uint8_t *bits, int n_qubits, int64_t nb, int q, const double *bra_mat,
-              double *site, int64_t stride, void *stream);
+              double *site, int64_t stride, int open, void *stream);
 void gate_apply(const double *in, double *out, int64_t nb, int64_t in_stride,
                 int64_t out_stride, SiteShape s, int leg, int chi, const double *g,
                 void *stream);
@@ -313,8 +319,10 @@ void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64
                     void *stream);
 void final_dot(const void *A, const void *Bt, double *partial, int64_t units, int64_t K,
                int64_t sA, int64_t sB, int c64, void *stream);
-void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices,
+void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices, int64_t per,
                void *stream);
+void finalize(const void *T, double *partial, int64_t units, int64_t t_us, int64_t per,
+              const Gather &g, int c64, void *stream);
 }  // namespace launch
 
 }  // namespace tns

@@ -558,18 +558,35 @@ __global__ __launch_bounds__(256) void k_final_dot(const R *__restrict__ A,
     }
 }
 
-// Pairwise (binary-counter) summation of the slices of each bitstring: a
-// fixed tree, so the result does not depend on launch configuration.
+// Last tensor of a unit with open legs -> its row of partial results, in
+// output order and widened to complex128.
+template <typename R>
+__global__ void k_finalize(const R *__restrict__ T, double *__restrict__ partial, int64_t units,
+                           int64_t t_us, int64_t per, Gather g) {
+    const int64_t total = units * per;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / per, i = t - u * per;
+        const R *src = T + 2 * (u * t_us + gather_offset(g, i));
+        partial[2 * t] = (double)src[0];
+        partial[2 * t + 1] = (double)src[1];
+    }
+}
+
+// Pairwise (binary-counter) summation of the slices of each (bitstring,
+// output) pair: a fixed tree, so the result does not depend on launch
+// configuration.  partial is [bitstring][slice][per].
 __global__ void k_slice_sum(const double *__restrict__ partial, double *__restrict__ amps,
-                            int64_t nb, int64_t n_slices) {
-    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= nb) return;
+                            int64_t nb, int64_t n_slices, int64_t per) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nb * per) return;
+    const int64_t b = t / per, o = t - b * per;
     double sr[64], si[64];
     int lv[64];
     int top = 0;
-    const double *x = partial + 2 * b * n_slices;
+    const double *x = partial + 2 * (b * n_slices * per + o);
     for (int64_t i = 0; i < n_slices; ++i) {
-        double vr = x[2 * i], vi = x[2 * i + 1];
+        double vr = x[2 * i * per], vi = x[2 * i * per + 1];
         int l = 0;
         while (top > 0 && lv[top - 1] == l) {
             vr = sr[top - 1] + vr;
@@ -591,8 +608,8 @@ __global__ void k_slice_sum(const double *__restrict__ partial, double *__restri
             ri = si[j] + ri;
         }
     }
-    amps[2 * b] = rr;
-    amps[2 * b + 1] = ri;
+    amps[2 * t] = rr;
+    amps[2 * t + 1] = ri;
 }
 
 }  // namespace
@@ -787,10 +804,23 @@ void final_dot(const void *A, const void *Bt, double *partial, int64_t units, in
     }
 }
 
-void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices, void *stream) {
-    hipLaunchKernelGGL(k_slice_sum, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0,
-                       (hipStream_t)stream, partial, amps, nb, n_slices);
+void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices, int64_t per,
+               void *stream) {
+    hipLaunchKernelGGL(k_slice_sum, dim3((unsigned)((nb * per + 63) / 64)), dim3(64), 0,
+                       (hipStream_t)stream, partial, amps, nb, n_slices, per);
     check_launch("slice_sum");
+}
+
+void finalize(const void *T, double *partial, int64_t units, int64_t t_us, int64_t per,
+              const Gather &g, int c64, void *stream) {
+    const int64_t total = units * per;
+    if (c64)
+        hipLaunchKernelGGL(k_finalize<float>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const float *)T, partial, units, t_us, per, g);
+    else
+        hipLaunchKernelGGL(k_finalize<double>, dim3(grid_for(total, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (const double *)T, partial, units, t_us, per, g);
+    check_launch("finalize");
 }
 
 }  // namespace launch

@@ -199,14 +199,24 @@ __global__ void k_init_ket(const double *ket_vec, int q, double *site) {
     if (threadIdx.x < 4) site[threadIdx.x] = ket_vec[4 * q + threadIdx.x];
 }
 
-// <s| H: row s_q of the trailing single-qubit product H
+// <s| H: row s_q of the trailing single-qubit product H.  For an open qubit
+// the output bit stays free: B[sigma][o] = H[o][sigma], an extra leg of size 2.
 __global__ void k_init_bra(const uint8_t *bits, int n_qubits, int64_t nb, int q,
-                           const double *bra_mat, double *site, int64_t stride) {
+                           const double *bra_mat, double *site, int64_t stride, int open) {
     int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
+    double *o = site + 2 * b * stride;
+    if (open) {
+        const double *h = bra_mat + 8 * q;   // H[r][c] at 2 * (2 r + c)
+        for (int sg = 0; sg < 2; ++sg)
+            for (int ob = 0; ob < 2; ++ob) {
+                o[2 * (2 * sg + ob)] = h[2 * (2 * ob + sg)];
+                o[2 * (2 * sg + ob) + 1] = h[2 * (2 * ob + sg) + 1];
+            }
+        return;
+    }
     const int s = bits[b * n_qubits + q] & 1;
     const double *h = bra_mat + 8 * q + 4 * s;
-    double *o = site + 2 * b * stride;
     o[0] = h[0]; o[1] = h[1]; o[2] = h[2]; o[3] = h[3];
 }
 
@@ -466,9 +476,9 @@ void init_ket(const double *ket_vec, int q, double *site, void *stream) {
 }
 
 void init_bra(const uint8_t *bits, int n_qubits, int64_t nb, int q, const double *bra_mat,
-              double *site, int64_t stride, void *stream) {
+              double *site, int64_t stride, int open, void *stream) {
     hipLaunchKernelGGL(k_init_bra, dim3(grid_for(nb, 256)), dim3(256), 0, (hipStream_t)stream,
-                       bits, n_qubits, nb, q, bra_mat, site, stride);
+                       bits, n_qubits, nb, q, bra_mat, site, stride, open);
     check_launch("init_bra");
 }
 

@@ -66,6 +66,9 @@ void validate_and_build(const tns_circuit_desc *desc, Circuit &c) {
             fail(TNS_E_UNSUPPORTED, "qubit " + std::to_string(q) + " has more than " +
                                         std::to_string(kMaxDeg) + " couplers");
     }
+    c.n_real_edges = (int)c.g.edges.size();
+    c.n_open = 0;
+    c.open_qubits.clear();
     c.gates.assign(desc->gates, desc->gates + desc->n_gates);
     c.max_cycle = 0;
     for (int i = 0; i < desc->n_gates; ++i) {
@@ -157,17 +160,20 @@ struct PG {
     std::vector<std::vector<int>> nbr;    // per node: neighbours
 };
 
+// A bond whose second endpoint is n is a dangling (open) leg of its first
+// endpoint: it is never contracted and connects nothing.
 PG make_pg(int n, const std::vector<std::pair<int, int>> &edges, const std::vector<double> &dims) {
     PG g;
     g.n = n;
-    g.legs.assign(n, {});
-    g.nbr.assign(n, {});
+    g.legs.assign(n + 1, {});
+    g.nbr.assign(n + 1, {});
     for (size_t e = 0; e < edges.size(); ++e) {
         if (!(dims[e] > 1.0)) continue;
         int id = (int)g.edges.size();
         g.edges.push_back(edges[e]);
         g.d.push_back(dims[e]);
         g.legs[edges[e].first].push_back(id);
+        if (edges[e].second == n) continue;
         g.legs[edges[e].second].push_back(id);
         g.nbr[edges[e].first].push_back(edges[e].second);
         g.nbr[edges[e].second].push_back(edges[e].first);
@@ -182,7 +188,7 @@ PG make_pg(int n, const std::vector<std::pair<int, int>> &edges, const std::vect
 // Score of a fixed order: sum of Cost(C^{set}, C^{j}) with Cost the product
 // of the dimensions of every bond carried by either tensor.
 double order_score(const PG &g, const std::vector<int> &order, double *peak, int *max_rank) {
-    std::vector<char> in(g.n, 0), open(g.edges.size(), 0);
+    std::vector<char> in(g.n + 1, 0), open(g.edges.size(), 0);
     double size = 1, score = 0, pk = 0;
     int rank = 0, mr = 0;
     for (size_t m = 0; m < order.size(); ++m) {
@@ -214,8 +220,8 @@ PathResult greedy(const PG &g) {
     const int n = g.n;
     for (int crit = 0; crit < 2; ++crit)
     for (int start = 0; start < n; ++start) {
-        std::vector<char> in(n, 0);
-        std::vector<int> adj(n, 0), order{start};
+        std::vector<char> in(n + 1, 0);
+        std::vector<int> adj(n + 1, 0), order{start};
         in[start] = 1;
         double size = 1, score = 0, peak = 0;
         int rank = 0, mr = 0;
@@ -319,7 +325,7 @@ PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_s
         pq.push({0.0, 1, seq++, (int32_t)arena.size() - 1});
     }
     PathResult res;
-    std::vector<char> in(n), open(g.edges.size()), adj(n), near(n);
+    std::vector<char> in(n + 1, 0), open(g.edges.size()), adj(n + 1), near(n + 1);
     while (!pq.empty()) {
         QItem it = pq.top();
         pq.pop();
@@ -508,6 +514,8 @@ SideEvolution evolve_side(const Plan &p, const std::vector<int> &fused_ids, bool
     const Circuit &c = p.circ;
     SideEvolution s;
     std::vector<int> dim(c.g.edges.size(), 1);
+    // open legs: absent (1) on the ket side, the bra's free output bit (2)
+    for (size_t e = c.n_real_edges; e < c.g.edges.size(); ++e) dim[e] = reverse ? 2 : 1;
     auto shape = [&](int q) {
         SiteShape sh{};
         sh.n = 1 + (int)c.g.legs[q].size();
@@ -516,6 +524,7 @@ SideEvolution evolve_side(const Plan &p, const std::vector<int> &fused_ids, bool
         return sh;
     };
     s.cap.assign(c.n, 2);
+    for (int q = 0; q < c.n; ++q) s.cap[q] = shape_elems(shape(q));
     std::vector<int> order = fused_ids;
     if (reverse) std::reverse(order.begin(), order.end());
     for (int fid : order) {
@@ -594,8 +603,9 @@ static void compile_steps(Plan &p) {
     std::vector<char> is_cut(c.g.edges.size(), 0);
     for (int e : p.cuts) is_cut[e] = 1;
     for (size_t e = 0; e < d.size(); ++e) d[e] = is_cut[e] ? 1 : p.bond_overlap[e];
-    std::vector<int> pos(n);
+    std::vector<int> pos(n + 1);
     for (int m = 0; m < n; ++m) pos[order[m]] = m;
+    pos[n] = std::numeric_limits<int>::max();   // open legs are never consumed
     auto consumed = [&](int e) { return std::max(pos[c.g.edges[e].first], pos[c.g.edges[e].second]); };
     auto logical_legs = [&](int q) {
         std::vector<int> v;
@@ -695,9 +705,11 @@ static void compile_steps(Plan &p) {
         }
         s.out_elems = s.M * s.N;
         const bool last = (m == n - 1);
-        if (last) {
+        if (last && c.n_open == 0) {
             if (s.M != 1 || s.N != 1) fail(TNS_E_BAD_PATH, "internal: final step is not a scalar");
             s.kernel = 2;
+        } else if (last && s.M * s.N != ((int64_t)1 << c.n_open)) {
+            fail(TNS_E_BAD_PATH, "internal: final tensor does not hold the open legs");
         } else if (s.K >= 16 && s.N >= 16 && s.M >= 16 && s.K % 2 == 0) {
             s.kernel = 0;
         } else {
@@ -712,6 +724,22 @@ static void compile_steps(Plan &p) {
         p.flops_per_amp += 8.0 * mkn;
         p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
         p.steps.push_back(s);
+    }
+    // open legs of the last tensor -> output order (first open qubit most significant)
+    p.out_per_unit = (int64_t)1 << c.n_open;
+    if (c.n_open > 0) {
+        std::vector<int64_t> tstride(T.size());
+        int64_t st = 1;
+        for (int i = (int)T.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[T[i]]; }
+        std::vector<int64_t> sz, sst;
+        for (int k = 0; k < c.n_open; ++k) {
+            const int e = c.n_real_edges + k;
+            const int i = (int)(std::find(T.begin(), T.end(), e) - T.begin());
+            if (i >= (int)T.size()) fail(TNS_E_BAD_PATH, "internal: open leg missing from the last tensor");
+            sz.push_back(2);
+            sst.push_back(tstride[i]);
+        }
+        p.final_perm = compact(sz, sst);
     }
     const double ns = (double)p.n_slices;
     p.flops_per_amp *= ns;
@@ -775,7 +803,7 @@ static std::vector<double> dims_with_cuts(const Plan &p, const std::vector<int> 
 static double largest_intermediate(const Circuit &c, const std::vector<double> &d,
                                    const std::vector<int> &order, std::vector<int> *open_out) {
     const auto &E = c.g.edges;
-    std::vector<char> in(c.n, 0);
+    std::vector<char> in(c.n + 1, 0);
     double best = -1;
     for (int j : order) {
         in[j] = 1;
@@ -818,6 +846,7 @@ static Sliced cuts_for_order(const Plan &p, const std::vector<int> &order, std::
         int be = -1;
         double bt = 0, bp = 0;
         for (int e : open) {
+            if (e >= c.n_real_edges) continue;   // open legs are not cut
             std::vector<double> dt = d;
             dt[e] = 1;
             double pke = 0;
@@ -848,8 +877,8 @@ static Sliced anneal_cuts(const Plan &p, double limit, int iters, uint64_t seed,
     const Circuit &c = p.circ;
     const auto &E = c.g.edges;
     std::vector<int> cand;
-    for (size_t e = 0; e < E.size(); ++e)
-        if (p.bond_overlap[e] > 1) cand.push_back((int)e);
+    for (int e = 0; e < c.n_real_edges; ++e)
+        if (p.bond_overlap[e] > 1) cand.push_back(e);
     std::mt19937_64 rng(seed);
     auto eval = [&](const std::vector<int> &cuts, std::vector<int> *ord) {
         PathResult r = path_search(c.n, E, dims_with_cuts(p, cuts), TNS_PATH_GREEDY, 0, true, 0);
@@ -915,7 +944,7 @@ static void choose_cuts_and_path(Plan &p) {
     if (p.opts.n_cuts >= 0) {
         for (int i = 0; i < p.opts.n_cuts; ++i) {
             int e = p.opts.cut_edges[i];
-            if (e < 0 || e >= (int)E.size() || std::count(given.begin(), given.end(), e))
+            if (e < 0 || e >= c.n_real_edges || std::count(given.begin(), given.end(), e))
                 fail(TNS_E_BAD_PATH, "bad cut edge " + std::to_string(e));
             given.push_back(e);
         }
@@ -985,13 +1014,31 @@ static void choose_cuts_and_path(Plan &p) {
     }
 }
 
+void add_open_legs(Circuit &c, const tns_plan_opts &opts) {
+    c.n_real_edges = (int)c.g.edges.size();
+    c.n_open = 0;
+    c.open_qubits.clear();
+    if (opts.n_open < 0 || opts.n_open > 20) fail(TNS_E_INVALID_ARG, "n_open must be in [0, 20]");
+    if (opts.n_open > 0 && !opts.open_qubits) fail(TNS_E_INVALID_ARG, "open_qubits is NULL");
+    for (int k = 0; k < opts.n_open; ++k) {
+        const int q = opts.open_qubits[k];
+        if (q < 0 || q >= c.n || std::count(c.open_qubits.begin(), c.open_qubits.end(), q))
+            fail(TNS_E_INVALID_ARG, "bad open qubit " + std::to_string(q));
+        if ((int)c.g.legs[q].size() + 1 > kMaxDeg) fail(TNS_E_UNSUPPORTED, "open qubit has too many legs");
+        c.open_qubits.push_back(q);
+        const int e = (int)c.g.edges.size();
+        c.g.edges.push_back({q, c.n});   // dangling: second endpoint is the virtual node n
+        c.g.legs[q].push_back(e);
+    }
+    c.n_open = opts.n_open;
+}
+
 void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
     p.circ = c;
     p.opts = opts;
     p.precision = opts.precision;
     if (opts.precision < TNS_C128 || opts.precision > TNS_C64_SPLIT_BF16_6)
         fail(TNS_E_INVALID_ARG, "unknown precision");
-    if (opts.n_open != 0 || opts.open_qubits) fail(TNS_E_UNSUPPORTED, "open qubits are reserved");
     if (opts.path) {
         std::vector<char> seen(c.n, 0);
         for (int i = 0; i < c.n; ++i) {

@@ -200,7 +200,7 @@ void plan_device_release(Plan &p) {
 
 int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget) {
     // half of the budget for per-bitstring tensors, the rest for work units
-    int64_t per = p.bytes_per_bitstring + p.n_slices * 16 + 32;
+    int64_t per = p.bytes_per_bitstring + p.n_slices * 16 * p.out_per_unit + 32;
     int64_t nb = (int64_t)(budget / 2) / std::max<int64_t>(per, 1);
     return std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
 }
@@ -244,7 +244,10 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
     const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget));
     const bool timing = true;
 
-    double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * 16, stream);
+    const int64_t opu = p.out_per_unit;   // amplitudes per bitstring (open qubits)
+    double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * opu * 16, stream);
+    std::vector<char> is_open(c.n, 0);
+    for (int q : c.open_qubits) is_open[q] = 1;
     for (int64_t b0 = 0; b0 < n; b0 += nb_max) {
         if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
         const int64_t nb = std::min(nb_max, n - b0);
@@ -273,7 +276,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         }
         for (int q = 0; q < c.n; ++q)
             launch::init_bra(bits_dev, c.n, nb, q, (const double *)p.d_bra_mat.ptr, sb.buf[0][q],
-                             p.bra.cap[q], stream);
+                             p.bra.cap[q], is_open[q], stream);
         st.launches += c.n;
         run_side(p, p.bra, sb, nb, vp, p.bra_scratch_elems, stream, st.launches);
         st.ms_bra += tb.stop();
@@ -301,7 +304,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         // ---- contraction of every (bitstring, slice) unit along the path
         Timer tc(stream, timing);
         const int64_t units = nb * n_sl;
-        double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * 16, stream);
+        double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * opu * 16, stream);
         const uint64_t used = ws.bytes;
         const uint64_t left = budget > used ? budget - used : 0;
         int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
@@ -365,11 +368,17 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 else
                     launch::final_dot(src, Bb, partial + 2 * ug0, g, s.K, peak, s.K, c64 ? 1 : 0, stream);
                 ev_end();
+                if (m + 1 == p.steps.size() && s.kernel != 2) {
+                    // open legs: the last tensor holds this unit's 2^open values
+                    launch::finalize(dst, partial + 2 * ug0 * opu, g, peak, opu, p.final_perm,
+                                     c64 ? 1 : 0, stream);
+                    st.launches += 1;
+                }
                 st.launches += 2;
                 cur = dst;
             }
         }
-        launch::slice_sum(partial, amps_dev + 2 * b0, nb, n_sl, stream);
+        launch::slice_sum(partial, amps_dev + 2 * b0 * opu, nb, n_sl, opu, stream);
         st.launches += 1;
         st.ms_contract += tc.stop();
         for (Ev &e : evs) {
@@ -384,7 +393,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         st.units += units;
         st.flops += p.flops_per_amp * nb * ((double)n_sl / (double)p.n_slices);
     }
-    hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * 16, hipMemcpyDeviceToHost,
+    hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * opu * 16, hipMemcpyDeviceToHost,
                              (hipStream_t)stream), "amplitude download");
     hip_check(hipStreamSynchronize((hipStream_t)stream), "amplitudes");
 }

@@ -148,6 +148,21 @@ def test_automatic_cuts_respect_limit(ctx):
     assert i.peak_elems <= 1 << 18 and i.n_slices > 1
 
 
+def test_open_qubits_plan(ctx):
+    c, _ = config("grid3x4_d8")
+    i0 = ctx.plan(c, split_cycle=4).info()
+    i1 = ctx.plan(c, split_cycle=4, open_qubits=[11, 0]).info()
+    assert list(i1.open_qubits) == [11, 0]
+    assert len(i1.bond_overlap) == len(i0.bond_overlap) + 2
+    # the open legs have dimension 2 on the bra side and 1 on the ket side
+    assert list(i1.bond_bra[-2:]) == [2, 2] and list(i1.bond_ket[-2:]) == [1, 1]
+    assert i1.flops_per_amp >= i0.flops_per_amp
+    for bad in ([12], [1, 1]):
+        with pytest.raises(T.TnsError) as e:
+            ctx.plan(c, open_qubits=bad)
+        assert e.value.name == "TNS_E_INVALID_ARG"
+
+
 # --- path search vs brute force (supplement, Algorithm 1 and Eq. (optscore))
 
 def _random_graph(seed, n):

@@ -106,6 +106,45 @@ def test_slice_ranges_add_up(ctx, small):
         ctx.amplitudes(p, bits, slices=(5, 5))
 
 
+def fill_open(bits, open_qubits):
+    """All bitstrings of each row with its open bits set to x = 0..2^k-1
+    (first open qubit most significant)."""
+    k = len(open_qubits)
+    out = np.repeat(bits[:, None, :], 1 << k, axis=1).copy()
+    for x in range(1 << k):
+        for i, q in enumerate(open_qubits):
+            out[:, x, q] = (x >> (k - 1 - i)) & 1
+    return out
+
+
+@pytest.mark.parametrize("prec,opts", [("c128", {}), ("c64", {}), ("c128", {"cuts": [2, 9]}),
+                                       ("c128", {"split_cycle": 0}), ("c128", {"split_cycle": 9})])
+def test_open_qubits_batch(ctx, prec, opts):
+    c, bits = config("grid3x4_d8", n_bits=8)
+    oq = [11, 0, 6]
+    full = fill_open(bits, oq)
+    ref = sv.amplitudes(c, full.reshape(-1, c.n)).reshape(len(bits), 8)
+    say("grid3x4_d8 open", oq, prec, opts)
+    p = ctx.plan(c, precision=prec, open_qubits=oq, **opts)
+    got = ctx.amplitudes(p, bits)
+    assert got.shape == (8, 8)
+    check(ref.reshape(-1), got.reshape(-1), c.n, prec)
+
+
+def test_open_qubits_53(ctx):
+    # 53 qubits, depth 8: 2^6 amplitudes per contraction against single ones
+    c = random_circuit(diagonal53(), 8, 31)
+    oq = [47, 48, 49, 50, 51, 52]
+    bits = bitstrings(53, 2, 32)
+    say("diag53 d8 open", oq)
+    p1 = ctx.plan(c, precision="c128")
+    po = ctx.plan(c, precision="c128", open_qubits=oq)
+    got = ctx.amplitudes(po, bits)
+    full = fill_open(bits, oq).reshape(-1, 53)
+    one = ctx.amplitudes(p1, full)
+    assert compare(one, got.reshape(-1), 53)["rel_l2"] <= 1e-10
+
+
 def test_no_final_layer(ctx):
     c, bits = config("grid3x4_d8", final_layer=False)
     ref = sv.amplitudes(c, bits)
