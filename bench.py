@@ -83,6 +83,106 @@ def serving_run(T, ctx, seconds_cap=20.0, n_req=40, seed=4):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
 
 
+def bench_53(T, ctx, args, torch):
+    """53-qubit diagonal lattice.  Depth 10: full amplitudes of random
+    bitstrings and a correlated batch (the 12 qubits the path absorbs last are
+    left open, one contraction gives 4096 amplitudes).  Depth 12: one amplitude
+    is ~1e17 flops, so a few slices of a contraction are timed (partial sums
+    over a slice range) and the full contraction is extrapolated; complex64,
+    split-BF16 and complex128 partial sums are compared."""
+    from circuits import config, random_circuit, diagonal53, bitstrings
+    out = {}
+    k_open = 12
+
+    def timed(plan, bits, slices=None):
+        ctx.amplitudes(plan, bits[:1], slices=(0, 1) if slices else None)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a, st = ctx.amplitudes(plan, bits, stats=True, slices=slices)
+        return a, time.perf_counter() - t, st
+
+    # ---- depth 10
+    try:
+        c10 = random_circuit(diagonal53(), 10, 3)
+        b10 = bitstrings(53, 64, 103)
+        res = {}
+        amps = {}
+        single = {}
+        for prec in ("c64", "c128"):
+            p10 = ctx.plan(c10, precision=prec)
+            amps[prec], dt, _ = timed(p10, b10)
+            i10 = p10.info()
+            single = i10
+            res[prec] = {"amps_per_s": round(len(b10) / dt, 2),
+                         "tflops": round(i10.flops_per_amp * len(b10) / dt / 1e12, 2)}
+            p10.close()
+        res["flops_per_amp"] = single.flops_per_amp
+        res["c64_rel_l2_vs_c128"] = rel_l2(amps["c128"], amps["c64"])
+        oq = [int(q) for q in single.path[-k_open:]]
+        corr = {"open_qubits": oq, "amplitudes_per_contraction": 1 << k_open}
+        ca = {}
+        for prec in ("c64", "c128"):
+            po = ctx.plan(c10, precision=prec, open_qubits=oq)
+            ca[prec], dt, _ = timed(po, b10[:4])
+            io = po.info()
+            corr[prec] = {"amps_per_s": round(4 * (1 << k_open) / dt, 1),
+                          "tflops": round(io.flops_per_amp * 4 / dt / 1e12, 2)}
+            corr["flops_per_contraction"] = io.flops_per_amp
+            po.close()
+        corr["c64_rel_l2_vs_c128"] = rel_l2(ca["c128"].reshape(-1), ca["c64"].reshape(-1))
+        res["correlated_batch"] = corr
+        out["diag53_d10"] = res
+        print("[bench] diag53_d10 done", file=sys.stderr, flush=True)
+    except Exception as e:
+        out["diag53_d10"] = {"error": str(e)}
+
+    # ---- depth 12
+    try:
+        c53, b53 = config("diag53_d12", n_bits=1)
+        res = {}
+        t = time.perf_counter()
+        p64 = ctx.plan(c53, precision="c64")
+        res["plan_s"] = round(time.perf_counter() - t, 2)
+        i53 = p64.info()
+        oq = [int(q) for q in i53.path[-k_open:]]
+        for label, opts in (("single", {}), ("correlated_batch", {"open_qubits": oq})):
+            base = p64 if not opts else ctx.plan(c53, precision="c64", **opts)
+            ib = base.info()
+            same = dict(split_cycle=int(ib.split_cycle), path=ib.path.tolist(),
+                        cuts=ib.cut_edges.tolist(), **opts)
+            ns = int(ib.n_slices)
+            nt = min(ns, args.d12_slices)
+            per = 1 << len(opts.get("open_qubits", []))
+            r = {"flops_per_contraction": ib.flops_per_amp, "amplitudes_per_contraction": per,
+                 "n_slices": ns, "split": int(ib.split_cycle), "peak_elems": int(ib.peak_elems),
+                 "slices_timed": nt}
+            parts = {}
+            for prec in ("c64", "c64_bf16x3", "c128"):
+                plan = base if prec == "c64" else ctx.plan(c53, precision=prec, **same)
+                a, dt, st = timed(plan, b53, slices=(0, nt))
+                parts[prec] = a.reshape(-1)
+                est = dt / nt * ns
+                r[prec] = {"s_per_slice": round(dt / nt, 3), "est_s_per_contraction": round(est, 1),
+                           "est_amps_per_s": round(per / est, 5),
+                           "tflops": round(ib.flops_per_amp * nt / ns / dt / 1e12, 2),
+                           "gemm_tflops": round(st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12, 2)
+                           if st["ms_gemm"] else None}
+                if plan is not base:
+                    plan.close()
+                print(f"[bench] diag53_d12 {label} {prec}: {dt / nt:.2f} s/slice", file=sys.stderr, flush=True)
+            for prec in ("c64", "c64_bf16x3"):
+                r[prec]["partial_rel_l2_vs_c128"] = rel_l2(parts["c128"], parts[prec])
+            if opts:
+                r["open_qubits"] = oq
+                base.close()
+            res[label] = r
+        p64.close()
+        out["diag53_d12"] = res
+    except Exception as e:
+        out["diag53_d12"] = {"error": str(e)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,75 +296,8 @@ def main():
                                 "f_ovl": float(abs(np.vdot(ref, test)) ** 2 / (np.vdot(ref, ref).real * np.vdot(test, test).real))}
         print(f"[bench] {other} done", file=sys.stderr, flush=True)
 
-    # 53 qubits at depth 12: one amplitude is ~1e17 flops, so a few of its
-    # slices are timed (partial sums over a slice range) and the full
-    # amplitude is extrapolated; c64, split-BF16 and c128 partial sums are
-    # compared with each other.
     if not args.no_d12:
-        try:
-            c53, b53 = config("diag53_d12", n_bits=1)
-            t = time.perf_counter()
-            p64 = ctx.plan(c53, precision="c64")
-            t_plan53 = time.perf_counter() - t
-            i53 = p64.info()
-            same = dict(split_cycle=int(i53.split_cycle), path=i53.path.tolist(),
-                        cuts=i53.cut_edges.tolist())
-            ns = int(i53.n_slices)
-            nt = min(ns, args.d12_slices)
-            res = {"flops_per_amp": i53.flops_per_amp, "n_slices": ns, "split": int(i53.split_cycle),
-                   "peak_elems": int(i53.peak_elems), "plan_s": round(t_plan53, 2), "slices_timed": nt}
-            parts = {}
-            for prec, plan53 in (("c64", p64), ("c64_bf16x3", None), ("c128", None)):
-                if plan53 is None:
-                    plan53 = ctx.plan(c53, precision=prec, **same)
-                ctx.amplitudes(plan53, b53, slices=(0, 1))          # warm-up: one slice
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                a, st = ctx.amplitudes(plan53, b53, slices=(0, nt), stats=True)
-                dt53 = time.perf_counter() - t
-                parts[prec] = a
-                fl = i53.flops_per_amp * nt / ns
-                res[prec] = {"s_per_slice": round(dt53 / nt, 3), "est_s_per_amp": round(dt53 / nt * ns, 1),
-                             "tflops": round(fl / dt53 / 1e12, 2),
-                             "gemm_tflops": round(st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12, 2)
-                             if st["ms_gemm"] else None}
-                if plan53 is not p64:
-                    plan53.close()
-                print(f"[bench] diag53_d12 {prec}: {dt53 / nt:.2f} s/slice", file=sys.stderr, flush=True)
-            ref = parts["c128"]
-            for prec in ("c64", "c64_bf16x3"):
-                res[prec]["partial_rel_err_vs_c128"] = float(abs(parts[prec][0] - ref[0]) / abs(ref[0]))
-            extra["diag53_d12"] = res
-            p64.close()
-        except Exception as e:  # a failure here is reported, not fatal
-            extra["diag53_d12"] = {"error": str(e)}
-
-    # 53 qubits at depth 10 (the deepest column of the paper's single-amplitude
-    # table): full amplitudes, c64 and c128
-    if not args.no_d12:
-        try:
-            c10 = random_circuit(diagonal53(), 10, 3)
-            b10 = bitstrings(53, 64, 103)
-            res = {}
-            amps10 = {}
-            for prec in ("c64", "c128"):
-                p10 = ctx.plan(c10, precision=prec)
-                ctx.amplitudes(p10, b10[:2])
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                amps10[prec] = ctx.amplitudes(p10, b10)
-                dt10 = time.perf_counter() - t
-                i10 = p10.info()
-                res[prec] = {"amps_per_s": round(len(b10) / dt10, 2),
-                             "tflops": round(i10.flops_per_amp * len(b10) / dt10 / 1e12, 2)}
-                res["flops_per_amp"] = i10.flops_per_amp
-                p10.close()
-            res["c64_rel_l2_vs_c128"] = rel_l2(amps10["c128"], amps10["c64"])
-            res["bitstrings"] = len(b10)
-            extra["diag53_d10"] = res
-            print(f"[bench] diag53_d10 done", file=sys.stderr, flush=True)
-        except Exception as e:
-            extra["diag53_d10"] = {"error": str(e)}
+        extra.update(bench_53(T, ctx, args, torch))
 
     if not args.no_serving:
         extra["serving"] = serving_run(T, ctx)
