@@ -264,12 +264,16 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
 // 4 waves in a WGM x WGN layout; each wave owns BI x BJ blocks of 32 x 32, so
 // the tile is (WGM*BI*32) x (WGN*BJ*32), k-step 32.  The next k-tile is
 // fetched into registers while the current one is multiplied out of LDS.
+// NSTAGE = 2 keeps two LDS k-tiles, so the next one is stored while the
+// current one is read and a k-step needs one barrier; it doubles the LDS of a
+// block, which pays where two blocks still fit on a CU (the 128 x 128 tile)
+// and costs occupancy on the narrow tiles, which keep NSTAGE = 1.
 // MODE 1: FP32 operands, v_mfma_f32_32x32x2f32; the two k-slots of an MFMA
 // (lanes 0-31 / 32-63) take k = 4*slot + t for the four MFMAs t of an
 // 8-wide k group, so each lane reads its values with one 16-byte LDS load.
 // MODE 2 / 3: split-BF16 with 3 / 6 products, v_mfma_f32_32x32x16_bf16, a
 // lane supplying 8 consecutive k of its row (A) and of its column (B).
-template <int BI, int BJ, int WGM, int WGN, int MODE>
+template <int BI, int BJ, int WGM, int WGN, int MODE, int NSTAGE>
 __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                                                    const float *__restrict__ Bt,
                                                    float *__restrict__ C, int64_t M, int Kr, int Nr,
@@ -280,8 +284,9 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     constexpr int LD = MODE == 1 ? G_BK + 4 : G_BK + 8;   // padded row (elements)
     using ET = typename std::conditional<MODE == 1, float, __bf16>::type;
     constexpr int APART = BM * LD, BPART = BN * LD;
-    __shared__ ET As[NSPLIT * APART];
-    __shared__ ET Bs[NSPLIT * BPART];
+    static_assert(NSTAGE == 1 || NSTAGE == 2, "one or two LDS stages");
+    __shared__ ET As[NSTAGE][NSPLIT * APART];
+    __shared__ ET Bs[NSTAGE][NSPLIT * BPART];
     constexpr int AV = BM / 32, BV = BN / 32;   // float4 loads per thread
     const int64_t u = blockIdx.y;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -317,26 +322,29 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
             if (gn < Nr && gk < Kr) rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int stage) {
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
-            ET *dst = &As[(lrow + 32 * i) * LD + lcol];
+            ET *dst = &As[stage][(lrow + 32 * i) * LD + lcol];
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = ra[i];
             else split_store<NSPLIT>(dst, APART, ra[i]);
         }
 #pragma unroll
         for (int i = 0; i < BV; ++i) {
-            ET *dst = &Bs[(lrow + 32 * i) * LD + lcol];
+            ET *dst = &Bs[stage][(lrow + 32 * i) * LD + lcol];
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = rb[i];
             else split_store<NSPLIT>(dst, BPART, rb[i]);
         }
     };
     fetch(0);
-    stash();
+    stash(0);
     __syncthreads();
+    int stage = 0;
     for (int k0 = 0; k0 < Kr; k0 += G_BK) {
         const bool more = k0 + G_BK < Kr;
         if (more) fetch(k0 + G_BK);
+        const ET *Ac = As[stage];
+        const ET *Bc = Bs[stage];
         if constexpr (MODE == 1) {
 #pragma unroll
             for (int kk = 0; kk < G_BK; kk += 8) {
@@ -344,10 +352,10 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                 v4f a[BI], b[BJ];
 #pragma unroll
                 for (int i = 0; i < BI; ++i)
-                    a[i] = *reinterpret_cast<const v4f *>(&As[(wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
+                    a[i] = *reinterpret_cast<const v4f *>(&Ac[(wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
 #pragma unroll
                 for (int j = 0; j < BJ; ++j)
-                    b[j] = *reinterpret_cast<const v4f *>(&Bs[(wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
+                    b[j] = *reinterpret_cast<const v4f *>(&Bc[(wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -366,11 +374,11 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 #pragma unroll
                     for (int i = 0; i < BI; ++i)
                         a[i][p] = *reinterpret_cast<const bf16x8 *>(
-                            &As[p * APART + (wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
+                            &Ac[p * APART + (wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
 #pragma unroll
                     for (int j = 0; j < BJ; ++j)
                         b[j][p] = *reinterpret_cast<const bf16x8 *>(
-                            &Bs[p * BPART + (wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
+                            &Bc[p * BPART + (wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
                 }
 #pragma unroll
                 for (int i = 0; i < BI; ++i)
@@ -388,10 +396,17 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                     }
             }
         }
-        __syncthreads();
-        if (more) {
-            stash();
+        if constexpr (NSTAGE == 2) {
+            // the other stage was last read before the previous barrier
+            if (more) stash(stage ^ 1);
             __syncthreads();
+            stage ^= 1;
+        } else {
+            __syncthreads();
+            if (more) {
+                stash(0);
+                __syncthreads();
+            }
         }
     }
     // 32x32 accumulator layout: lane holds column lane%32 and rows
@@ -720,15 +735,18 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
     check_launch("build_b");
 }
 
+// NSTAGE: two LDS stages on the 128 x 128 tile for FP32 and 3-product BF16
+// (73.7 / 81.9 KB, two blocks per CU); one elsewhere.
 template <int BI, int BJ, int WGM, int WGN>
 static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
                        int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+    constexpr int S = WGN == 2 ? 2 : 1;
     if (mode == 1)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
     else if (mode == 2)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
     else
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, 1>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
 }
 
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
