@@ -220,8 +220,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-constexpr int G_BK = 32;   // k-step (reals) of the FP32 and split-BF16 kernels
-
 // Tile order: consecutive workgroup ids are dispatched round-robin over the
 // 8 XCDs, each with its own L2.  Remap so that each XCD receives a contiguous
 // run of logical tiles (row-major over (tile_m, tile_n)), i.e. the tiles that
@@ -262,7 +260,7 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
 
 // C[M][Nr] = A[M][Kr] * Bt[Nr][Kr]^T, row-major, Kr % 4 == 0.  256 threads =
 // 4 waves in a WGM x WGN layout; each wave owns BI x BJ blocks of 32 x 32, so
-// the tile is (WGM*BI*32) x (WGN*BJ*32), k-step 32.  The next k-tile is
+// the tile is (WGM*BI*32) x (WGN*BJ*32), k-step BK reals.  The next k-tile is
 // fetched into registers while the current one is multiplied out of LDS.
 // NSTAGE = 2 keeps two LDS k-tiles, so the next one is stored while the
 // current one is read and a k-step needs one barrier; it doubles the LDS of a
@@ -273,7 +271,7 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
 // 8-wide k group, so each lane reads its values with one 16-byte LDS load.
 // MODE 2 / 3: split-BF16 with 3 / 6 products, v_mfma_f32_32x32x16_bf16, a
 // lane supplying 8 consecutive k of its row (A) and of its column (B).
-template <int BI, int BJ, int WGM, int WGN, int MODE, int NSTAGE>
+template <int BI, int BJ, int WGM, int WGN, int MODE, int NSTAGE, int BK>
 __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                                                    const float *__restrict__ Bt,
                                                    float *__restrict__ C, int64_t M, int Kr, int Nr,
@@ -281,13 +279,19 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     static_assert(WGM * WGN == 4, "four waves");
     constexpr int BM = WGM * BI * 32, BN = WGN * BJ * 32;
     constexpr int NSPLIT = MODE == 1 ? 1 : MODE;          // 1, 2 or 3 parts
-    constexpr int LD = MODE == 1 ? G_BK + 4 : G_BK + 8;   // padded row (elements)
+    static_assert(BK == 16 || BK == 32, "k-step of 16 or 32 reals");
+    constexpr int LD = MODE == 1 ? BK + 4 : BK + 8;   // padded row (elements)
     using ET = typename std::conditional<MODE == 1, float, __bf16>::type;
     constexpr int APART = BM * LD, BPART = BN * LD;
     static_assert(NSTAGE == 1 || NSTAGE == 2, "one or two LDS stages");
     __shared__ ET As[NSTAGE][NSPLIT * APART];
     __shared__ ET Bs[NSTAGE][NSPLIT * BPART];
-    constexpr int AV = BM / 32, BV = BN / 32;   // float4 loads per thread
+    // a k-tile row is BK/4 float4; 256 threads cover RPP rows per pass;
+    // float4 loads per thread, a B tile narrower than one pass leaving the
+    // threads with lrow >= BN idle
+    constexpr int TPR = BK / 4, RPP = 256 / TPR;
+    constexpr int AV = BM / RPP, BV = (BN + RPP - 1) / RPP;
+    constexpr bool BPART_PASS = BN % RPP != 0;
     const int64_t u = blockIdx.y;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
@@ -305,33 +309,34 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
         for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    const int lrow = tid >> 3, lcol = (tid & 7) * 4;
+    const int lrow = tid / TPR, lcol = (tid % TPR) * 4;
     v4f ra[AV], rb[BV];
     auto fetch = [&](int k0) {
         const int gk = k0 + lcol;
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
-            const int64_t gm = m0 + lrow + 32 * i;
+            const int64_t gm = m0 + lrow + RPP * i;
             ra[i] = v4f{0.f, 0.f, 0.f, 0.f};
             if (gm < M && gk < Kr) ra[i] = *reinterpret_cast<const v4f *>(A + gm * Kr + gk);
         }
 #pragma unroll
         for (int i = 0; i < BV; ++i) {
-            const int gn = n0 + lrow + 32 * i;
+            const int gn = n0 + lrow + RPP * i;
             rb[i] = v4f{0.f, 0.f, 0.f, 0.f};
-            if (gn < Nr && gk < Kr) rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
+            if (gn < Nr && gk < Kr && (!BPART_PASS || lrow + RPP * i < BN)) rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
         }
     };
     auto stash = [&](int stage) {
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
-            ET *dst = &As[stage][(lrow + 32 * i) * LD + lcol];
+            ET *dst = &As[stage][(lrow + RPP * i) * LD + lcol];
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = ra[i];
             else split_store<NSPLIT>(dst, APART, ra[i]);
         }
 #pragma unroll
         for (int i = 0; i < BV; ++i) {
-            ET *dst = &Bs[stage][(lrow + 32 * i) * LD + lcol];
+            if (BPART_PASS && lrow + RPP * i >= BN) continue;
+            ET *dst = &Bs[stage][(lrow + RPP * i) * LD + lcol];
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = rb[i];
             else split_store<NSPLIT>(dst, BPART, rb[i]);
         }
@@ -340,14 +345,14 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     stash(0);
     __syncthreads();
     int stage = 0;
-    for (int k0 = 0; k0 < Kr; k0 += G_BK) {
-        const bool more = k0 + G_BK < Kr;
-        if (more) fetch(k0 + G_BK);
+    for (int k0 = 0; k0 < Kr; k0 += BK) {
+        const bool more = k0 + BK < Kr;
+        if (more) fetch(k0 + BK);
         const ET *Ac = As[stage];
         const ET *Bc = Bs[stage];
         if constexpr (MODE == 1) {
 #pragma unroll
-            for (int kk = 0; kk < G_BK; kk += 8) {
+            for (int kk = 0; kk < BK; kk += 8) {
                 const int kofs = kk + 4 * (lane >> 5);
                 v4f a[BI], b[BJ];
 #pragma unroll
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
             }
         } else {
 #pragma unroll
-            for (int kk = 0; kk < G_BK; kk += 16) {
+            for (int kk = 0; kk < BK; kk += 16) {
                 const int kofs = kk + 8 * (lane >> 5);
                 bf16x8 a[BI][NSPLIT], b[BJ][NSPLIT];
 #pragma unroll
@@ -423,94 +428,121 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
             }
 }
 
-// FP64 MFMA GEMM with v_mfma_f64_16x16x4f64: tile 64 x 64, k-step 16, four
-// waves in 2 x 2, each 32 x 32 as 2 x 2 blocks of 16 x 16.  The four k-slots
-// (lanes 16*slot .. 16*slot+15) map to k = 4*slot + t for the four MFMAs of a
-// 16-wide k group.
-constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16, F64_LD = F64_BK + 2;
+// FP64 MFMA GEMM with v_mfma_f64_16x16x4f64: four waves in 2 x 2, each
+// owning BI x BJ blocks of 16 x 16, so the tile is (32*BI) x (32*BJ), k-step
+// 16.  The four k-slots (lanes 16*slot .. 16*slot+15) map to k = 4*slot + t
+// for the four MFMAs t of a 16-wide k group.  The next k-tile is fetched into
+// registers during the current one's MFMAs; NSTAGE = 2 keeps two LDS stages
+// (one barrier per k-step) as in the FP32 kernel.
+constexpr int F64_BK = 16, F64_LD = F64_BK + 2;
 
+template <int BI, int BJ, int NSTAGE>
 __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
                                                    const double *__restrict__ Bt,
                                                    double *__restrict__ C, int64_t M, int Kr,
                                                    int Nr, int64_t sA, int64_t sB, int64_t sC,
                                                    int tiles_n) {
-    __shared__ double As[F64_BM * F64_LD];
-    __shared__ double Bs[F64_BN * F64_LD];
+    constexpr int BM = 32 * BI, BN = 32 * BJ;
+    constexpr int AP = BM / 64, BP = BN / 64;   // 64-row load passes per operand
+    static_assert(BM % 64 == 0 && BN % 64 == 0, "tile edges are multiples of 64");
+    __shared__ double As[NSTAGE][BM * F64_LD];
+    __shared__ double Bs[NSTAGE][BN * F64_LD];
     const int64_t u = blockIdx.y;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
-    const int64_t m0 = tm * F64_BM;
-    const int n0 = (int)tn * F64_BN;
+    const int64_t m0 = tm * BM;
+    const int n0 = (int)tn * BN;
     A += u * sA;
     Bt += u * sB;
     C += u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    v4d acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    v4d acc[BI][BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
     const int lrow = tid >> 2, lcol = (tid & 3) * 4;
-    v2d ra[2], rb[2];
+    v2d ra[AP][2], rb[BP][2];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int gk = k0 + lcol + 2 * h;
-            const int64_t gm = m0 + lrow;
-            ra[h] = v2d{0.0, 0.0};
-            if (gm < M && gk < Kr) ra[h] = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
-            const int gn = n0 + lrow;
-            rb[h] = v2d{0.0, 0.0};
-            if (gn < Nr && gk < Kr) rb[h] = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
+#pragma unroll
+            for (int p = 0; p < AP; ++p) {
+                const int64_t gm = m0 + lrow + 64 * p;
+                ra[p][h] = v2d{0.0, 0.0};
+                if (gm < M && gk < Kr) ra[p][h] = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
+            }
+#pragma unroll
+            for (int p = 0; p < BP; ++p) {
+                const int gn = n0 + lrow + 64 * p;
+                rb[p][h] = v2d{0.0, 0.0};
+                if (gn < Nr && gk < Kr) rb[p][h] = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
+            }
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int stage) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<v2d *>(&As[lrow * F64_LD + lcol + 2 * h]) = ra[h];
-            *reinterpret_cast<v2d *>(&Bs[lrow * F64_LD + lcol + 2 * h]) = rb[h];
+#pragma unroll
+            for (int p = 0; p < AP; ++p)
+                *reinterpret_cast<v2d *>(&As[stage][(lrow + 64 * p) * F64_LD + lcol + 2 * h]) = ra[p][h];
+#pragma unroll
+            for (int p = 0; p < BP; ++p)
+                *reinterpret_cast<v2d *>(&Bs[stage][(lrow + 64 * p) * F64_LD + lcol + 2 * h]) = rb[p][h];
         }
     };
     fetch(0);
-    stash();
+    stash(0);
     __syncthreads();
+    int stage = 0;
     for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
         const bool more = k0 + F64_BK < Kr;
         if (more) fetch(k0 + F64_BK);
+        const double *Ac = As[stage], *Bc = Bs[stage];
         const int kofs = 4 * (lane >> 4);
-        v4d a[2], b[2];
+        v4d a[BI], b[BJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const double *p = &As[(wm * 32 + i * 16 + (lane & 15)) * F64_LD + kofs];
-            a[i] = v4d{p[0], p[1], p[2], p[3]};
+        for (int i = 0; i < BI; ++i) {
+            const double *q = &Ac[(wm * BI * 16 + i * 16 + (lane & 15)) * F64_LD + kofs];
+            a[i] = v4d{q[0], q[1], q[2], q[3]};
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const double *p = &Bs[(wn * 32 + j * 16 + (lane & 15)) * F64_LD + kofs];
-            b[j] = v4d{p[0], p[1], p[2], p[3]};
+        for (int j = 0; j < BJ; ++j) {
+            const double *q = &Bc[(wn * BJ * 16 + j * 16 + (lane & 15)) * F64_LD + kofs];
+            b[j] = v4d{q[0], q[1], q[2], q[3]};
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < BJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
-        __syncthreads();
-        if (more) {
-            stash();
+        if constexpr (NSTAGE == 2) {
+            if (more) stash(stage ^ 1);
             __syncthreads();
+            stage ^= 1;
+        } else {
+            __syncthreads();
+            if (more) {
+                stash(0);
+                __syncthreads();
+            }
         }
     }
     // 16x16 f64 accumulator layout: lane holds column lane%16 and rows lane/16 + 4*r.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
-                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                const int64_t row = m0 + wm * BI * 16 + i * 16 + (lane >> 4) + 4 * r;
+                const int col = n0 + wn * BJ * 16 + j * 16 + (lane & 15);
                 if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
             }
 }
@@ -735,18 +767,19 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
     check_launch("build_b");
 }
 
-// NSTAGE: two LDS stages on the 128 x 128 tile for FP32 and 3-product BF16
-// (73.7 / 81.9 KB, two blocks per CU); one elsewhere.
+// NSTAGE: two LDS stages on the 128 x 128 tile (k-step 32: 73.7 KB FP32,
+// 81.9 KB 3-product BF16; the 6-product form takes k-step 16, 61.4 KB), so
+// two blocks fit on a CU; one stage on the narrow tiles.
 template <int BI, int BJ, int WGM, int WGN>
 static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
                        int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
     constexpr int S = WGN == 2 ? 2 : 1;
     if (mode == 1)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
     else if (mode == 2)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 32>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
     else
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, 1>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, S, (S == 2 ? 16 : 32)>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
 }
 
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
@@ -757,10 +790,13 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     const int c64 = mode != 0;
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
-    // tile shape: 256 x 32 for N <= 16 complex, 256 x 64 for N <= 32, else 128 x 128
-    const int shape = !c64 ? 0 : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : 3));
-    const int BM = shape == 0 ? F64_BM : (shape == 3 ? 128 : 256);
-    const int BN = shape == 0 ? F64_BN : (shape == 1 ? 32 : (shape == 2 ? 64 : 128));
+    // tile shape: complex64 256 x 32 for N <= 16 complex, 256 x 64 for N <= 32,
+    // else 128 x 128; complex128 128 x 128 for N >= 128 complex and M >= 4096,
+    // else 64 x 64 (measured: the large tile loses on narrow and short shapes)
+    const bool f64_big = Nr >= 256 && M >= 4096;
+    const int shape = !c64 ? (f64_big ? 4 : 0) : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : 3));
+    const int BM = shape == 0 ? 64 : (shape == 3 || shape == 4 ? 128 : 256);
+    const int BN = shape == 0 ? 64 : (shape == 1 ? 32 : (shape == 2 ? 64 : 128));
     const int tiles_n = (Nr + BN - 1) / BN;
     // rows per launch so that the grid stays below 2^31 blocks
     const int64_t max_tiles_m = ((int64_t)1 << 30) / tiles_n;
@@ -780,11 +816,15 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
                 else if (shape == 2) launch_c64<2, 2, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
                 else launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
             } else {
-                hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st,
-                                   (const double *)A + 2 * (u0 * sA + r0 * K),
-                                   (const double *)Bt + 4 * u0 * sB,
-                                   (double *)C + 2 * (u0 * sC + r0 * N), mr, Kr, Nr, 2 * sA, 4 * sB,
-                                   2 * sC, tiles_n);
+                const double *a = (const double *)A + 2 * (u0 * sA + r0 * K);
+                const double *b = (const double *)Bt + 4 * u0 * sB;
+                double *c = (double *)C + 2 * (u0 * sC + r0 * N);
+                if (shape == 4)
+                    hipLaunchKernelGGL((k_gemm_f64<4, 4, 2>), grid, dim3(256), 0, st, a, b, c, mr, Kr, Nr,
+                                       2 * sA, 4 * sB, 2 * sC, tiles_n);
+                else
+                    hipLaunchKernelGGL((k_gemm_f64<2, 2, 2>), grid, dim3(256), 0, st, a, b, c, mr, Kr, Nr,
+                                       2 * sA, 4 * sB, 2 * sC, tiles_n);
             }
             check_launch("gemm");
         }
