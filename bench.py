@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # are in profiles/gemm_f32_grid5x5_d10_traffic.md).  Keyed by the sha256
 # prefix of the kernel source the counters were taken on: any change to the
 # kernels makes the entry stale and the bench reports null.
-MEASURED_TRAFFIC = {("c64", "grid5x5_d10", "45421e567022a4df"): 1001.7 * 2 ** 20}
+MEASURED_TRAFFIC = {("c64", "grid5x5_d10", "287c8c440451e88f"): 1005.9 * 2 ** 20}
 
 
 def rel_l2(a, b):
@@ -46,31 +46,85 @@ def xeb(a, b, n):
     return float((np.mean(p * q) - 1) / (np.mean(p * p) - 1))
 
 
-def serving_run(T, ctx, seconds_cap=20.0, n_req=40, seed=4):
-    """Short continuous-batching run: Poisson arrivals of requests on seeded
-    random circuits of 12-25 qubits, depths 6-10, 1-64 bitstrings each."""
-    from circuits import grid, random_circuit, bitstrings
+def serving_pool(T, size, seed):
+    """Seeded circuits of the serving mix: 20-53 qubits, half on the first N
+    sites of a floor(sqrt(N))-row grid, half on the first N sites of the
+    53-qubit diagonal lattice, depths 6-12."""
+    import math
+    from circuits import grid, diagonal53, random_circuit
     rng = np.random.default_rng(seed)
-    shapes = [(3, 4), (4, 4), (4, 5), (5, 5)]
-    plans = {}
-    reqs = []
+    pool = []
+    for i in range(size):
+        kind = "grid" if rng.random() < 0.5 else "diag"
+        n = int(rng.integers(20, 54))
+        d = int(rng.integers(6, 13))
+        r = math.isqrt(n)
+        lat = grid(r, -(-n // r)).sub(n) if kind == "grid" else diagonal53().sub(n)
+        pool.append((f"{kind}{n}_d{d}", random_circuit(lat, d, 4000 + i)))
+    return pool, rng
+
+
+def serving_run(T, ctx, torch, n_req=100, pool_size=24, cap_gpu_s=5.0, nominal_tflops=100.0,
+                load=0.7, seed=4, max_elems=1 << 32):
+    """Continuous batching on the serving mix (complex64).  The pool's plans
+    are compiled ahead and stay resident.  Admission: a request whose planned
+    work (flops per amplitude x bitstrings) exceeds cap_gpu_s at
+    nominal_tflops, or whose circuit needs cuts to fit max_elems, is rejected
+    and counted; the library itself rejects requests that do not fit a
+    serving slot's memory.  Bitstrings per request are log-uniform in
+    1..1024.  Arrivals are Poisson at the rate that gives the stated offered
+    load, from service times measured on the device before the run."""
+    import math
+    from circuits import bitstrings
+    pool, rng = serving_pool(T, pool_size, seed)
+    pctx = T.Context(-1)
+    plans = []
+    for name, circ in pool:
+        # screen with the unsliced cost (no cut search) on the host planner
+        q = pctx.plan(circ, precision="c64", max_intermediate_elems=1 << 62, path_mode="greedy")
+        qi = q.info()
+        fl, pk = qi.flops_per_amp, int(qi.peak_elems)
+        q.close()
+        if pk > max_elems or fl / (nominal_tflops * 1e12) > cap_gpu_s:
+            plans.append((name, circ, None, fl, None))
+            continue
+        p = ctx.plan(circ, precision="c64")
+        # service-time model o + a * n from one and four bitstrings
+        b = bitstrings(circ.n, 4, 9000)
+        ctx.amplitudes(p, b[:1])
+        torch.cuda.synchronize()
+        t = time.perf_counter(); ctx.amplitudes(p, b[:1]); t1 = time.perf_counter() - t
+        t = time.perf_counter(); ctx.amplitudes(p, b); t4 = time.perf_counter() - t
+        a = max((t4 - t1) / 3, 0.0)
+        plans.append((name, circ, p, p.info().flops_per_amp, (max(t1 - a, 0.0), a)))
+    pctx.close()
+    reqs, rejected_work = [], 0
     for i in range(n_req):
-        r, c = shapes[int(rng.integers(len(shapes)))]
-        d = int(rng.integers(6, 11))
-        key = (r, c, d)
-        if key not in plans:
-            circ = random_circuit(grid(r, c), d, 1000 + len(plans))
-            plans[key] = (circ, ctx.plan(circ, precision="c64"))
-        nb = int(np.exp(rng.uniform(0, np.log(64))))
-        reqs.append((key, bitstrings(r * c, nb, 2000 + i)))
-    gaps = rng.exponential(0.05, size=n_req)
+        k = int(rng.integers(len(plans)))
+        nb = int(min(1024, max(1, round(math.exp(rng.uniform(0, math.log(1024)))))))
+        name, circ, p, fl, model = plans[k]
+        if p is None or fl * nb / (nominal_tflops * 1e12) > cap_gpu_s:
+            rejected_work += 1
+            continue
+        reqs.append((k, bitstrings(circ.n, nb, 20000 + i), model[0] + model[1] * nb))
+    mean_service = float(np.mean([r[2] for r in reqs]))
+    rate = load / mean_service
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    torch.cuda.synchronize()
+    handles, rejected_mem = [], 0
     t0 = time.perf_counter()
-    handles = []
-    for (key, bits), gap in zip(reqs, gaps):
-        time.sleep(gap)
-        handles.append(ctx.submit(plans[key][1], bits))
-        if time.perf_counter() - t0 > seconds_cap:
-            break
+    t_next = t0
+    for (k, bits, _), gap in zip(reqs, gaps):
+        t_next += gap
+        delay = t_next - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        try:
+            handles.append(ctx.submit(plans[k][2], bits))
+        except T.TnsError as e:
+            if e.name != "TNS_E_ADMISSION":
+                raise
+            rejected_mem += 1
     total_amps = 0
     lat = []
     for h in handles:
@@ -78,9 +132,64 @@ def serving_run(T, ctx, seconds_cap=20.0, n_req=40, seed=4):
         total_amps += h.bits.shape[0]
         lat.append(h.latency_ms()[0])
     wall = time.perf_counter() - t0
+    for _, _, p, _, _ in plans:
+        if p is not None:
+            p.close()
     lat = np.array(lat)
-    return {"requests": len(handles), "amps_per_s": total_amps / wall,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+    return {"mix": "20-53 qubits (grid / diagonal lattice), depths 6-12, 1-1024 bitstrings, c64",
+            "arrivals": n_req, "served": len(handles), "rejected_work_cap": rejected_work,
+            "rejected_memory": rejected_mem, "work_cap_gpu_s": cap_gpu_s,
+            "pool": [n for n, _, _, _, _ in plans],
+            "pool_rejected": [n for n, _, p, _, _ in plans if p is None],
+            "offered_load": load, "mean_service_ms": round(mean_service * 1e3, 2),
+            "wall_s": round(wall, 2), "amps_per_s": round(total_amps / wall, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+
+
+def bench_104(T, ctx, args, torch):
+    """104 qubits on the 8x13 grid, 8 cycles: a few bitstrings of the
+    256-bitstring batch timed in complex64, split-BF16 and complex128, with
+    the complex64 and split-BF16 amplitudes compared to complex128."""
+    from circuits import config
+    out = {}
+    circ, bits = config("grid8x13_d8")
+    t = time.perf_counter()
+    base = ctx.plan(circ, precision="c64")
+    out["plan_s"] = round(time.perf_counter() - t, 2)
+    ib = base.info()
+    same = dict(split_cycle=int(ib.split_cycle), path=ib.path.tolist(), cuts=ib.cut_edges.tolist())
+    out.update({"flops_per_amp": ib.flops_per_amp, "n_slices": int(ib.n_slices),
+                "split": int(ib.split_cycle), "peak_elems": int(ib.peak_elems),
+                "batch": int(len(bits))})
+    nb = args.b104_bits
+    amps = {}
+    for prec in ("c64", "c64_bf16x3", "c128"):
+        plan = base if prec == "c64" else ctx.plan(circ, precision=prec, **same)
+        sub = bits[:nb if prec != "c128" else max(1, nb // 2)]
+        ctx.amplitudes(plan, sub[:1])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a, st = ctx.amplitudes(plan, sub, stats=True)
+        dt = time.perf_counter() - t
+        amps[prec] = a
+        out[prec] = {"bitstrings_timed": int(len(sub)), "amps_per_s": round(len(sub) / dt, 4),
+                     "est_s_per_batch": round(dt / len(sub) * len(bits), 1),
+                     "tflops": round(ib.flops_per_amp * len(sub) / dt / 1e12, 2),
+                     "gemm_tflops": round(st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12, 2)
+                     if st["ms_gemm"] else None,
+                     "ms_per_amp": {k: round(st[k] / len(sub), 1) for k in
+                                    ("ms_total", "ms_gemm", "ms_permute", "ms_small", "ms_bra", "ms_merge")},
+                     "permute_GBps": round(st["permute_bytes"] / (st["ms_permute"] * 1e-3) / 1e9, 1)
+                     if st["ms_permute"] else None}
+        if plan is not base:
+            plan.close()
+        print(f"[bench] grid8x13_d8 {prec}: {len(sub) / dt:.3f} amps/s", file=sys.stderr, flush=True)
+    k = len(amps["c128"])
+    for prec in ("c64", "c64_bf16x3"):
+        out[prec]["rel_l2_vs_c128"] = rel_l2(amps["c128"], amps[prec][:k])
+    base.close()
+    return {"grid8x13_d8": out}
 
 
 def bench_53(T, ctx, args, torch):
@@ -196,6 +305,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-d12", action="store_true", help="skip the 53-qubit depth-12 slice timing")
     ap.add_argument("--d12-slices", type=int, default=2)
+    ap.add_argument("--no-104", action="store_true", help="skip the 104-qubit grid leg")
+    ap.add_argument("--b104-bits", type=int, default=4, help="bitstrings timed on the 104-qubit grid")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB of a plain device copy run first (byte-counter calibration)")
     args = ap.parse_args()
@@ -248,8 +359,9 @@ def main():
 
     gemm_tflops = agg["gemm_flops"] / (agg["ms_gemm"] * 1e-3) / 1e12 if agg.get("ms_gemm") else 0.0
     avg_gemm_ms = agg["ms_gemm"] / max(agg["gemm_launches"], 1)
-    kname = {"c64": "k_gemm_f32", "c128": "k_gemm_f64", "c64_bf16x3": "k_gemm_bf16<2>",
-             "c64_bf16x6": "k_gemm_bf16<3>"}[args.precision]
+    kname = {"c64": "k_gemm_c64 (MODE 1, FP32 MFMA)", "c128": "k_gemm_f64 (FP64 MFMA)",
+             "c64_bf16x3": "k_gemm_c64 (MODE 2, split-BF16 x3)",
+             "c64_bf16x6": "k_gemm_c64 (MODE 3, split-BF16 x6)"}[args.precision]
     import hashlib
     src = os.path.join(ROOT, "paper_2011_02621_amd", "csrc", "kernels_contract.hip")
     src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -299,8 +411,14 @@ def main():
     if not args.no_d12:
         extra.update(bench_53(T, ctx, args, torch))
 
+    if not args.no_104:
+        try:
+            extra.update(bench_104(T, ctx, args, torch))
+        except Exception as e:
+            extra["grid8x13_d8"] = {"error": str(e)}
+
     if not args.no_serving:
-        extra["serving"] = serving_run(T, ctx)
+        extra["serving"] = serving_run(T, ctx, torch)
         print(f"[bench] serving done", file=sys.stderr, flush=True)
 
     cpu = None

@@ -139,7 +139,8 @@ typedef struct {
     const int64_t *step_k;          /* [n_steps] shared-bond product */
     const int64_t *step_n;          /* [n_steps] new-leg product */
     const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM, 1 small, 2 final dot */
-    const int32_t *step_permute;    /* [n_steps] 1 if the boundary tensor is permuted */
+    const int32_t *step_permute;    /* [n_steps] 0 no permute, 1 permute launch, 2 permute done
+                                       by the previous GEMM's store (fused) */
     const int32_t *bond_ket;        /* [n_edges] ket bond dimensions */
     const int32_t *bond_bra;        /* [n_edges] bra bond dimensions */
     const int32_t *bond_overlap;    /* [n_edges] overlap bond dimensions */
@@ -148,7 +149,7 @@ typedef struct {
     int64_t n_slices;
     double flops_per_amp;           /* 8 * sum over slices and steps of M*K*N */
     double gemm_bytes_per_amp;      /* element bytes * sum (MK + KN + MN) */
-    double permute_bytes_per_amp;   /* 2 * element bytes * permuted elements */
+    double permute_bytes_per_amp;   /* 2 * element bytes * elements of the permute launches */
     double path_score;              /* sum of M*K*N of one slice (the supplement's score) */
     int64_t peak_elems;             /* largest intermediate of one slice */
     int64_t device_bytes_resident;  /* ket tensors and plan tables */
@@ -242,7 +243,12 @@ tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n,
 
 /* Asynchronous request: queued, admitted by memory, and executed by the
  * context's worker threads, which interleave work units of concurrent
- * requests on several streams.  bits and amps must stay valid until done. */
+ * requests on several streams.  bits and amps must stay valid until done.
+ * The first call starts three workers; the context's HBM budget is then
+ * split into four equal slots, one per worker and one for synchronous calls
+ * on the same context (a larger cached synchronous workspace is released).
+ * A request whose one-bitstring chunk does not fit a slot fails with
+ * TNS_E_ADMISSION. */
 tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                       const uint8_t *bits, double *amps, tns_request **out);
 tns_status tns_poll(tns_request *req, int *done);   /* *done = 1 when finished */

@@ -402,7 +402,10 @@ static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n,
             std::lock_guard<std::mutex> lk(ctx->mu);
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
             void *st = hip_stream ? hip_stream : ctx->stream;
-            run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, ctx->budget, slice_begin,
+            // once serving workers exist, synchronous calls take one slot's
+            // share of the budget, like each worker
+            const uint64_t budget = ctx->server ? ctx->server->worker_budget : ctx->budget;
+            run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, budget, slice_begin,
                            slice_end);
         }
         if (stats) {
@@ -457,6 +460,12 @@ tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8
             if (!ctx->server) {
                 ctx->server = new Server();
                 ctx->server->start(ctx, 3);
+                // the synchronous workspace may have grown to the whole budget;
+                // from now on it shares the budget with the workers
+                if ((uint64_t)ctx->ws.bytes > ctx->server->worker_budget) {
+                    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+                    ctx->ws.release(ctx, ctx->stream);
+                }
             }
         }
         Server *sv = ctx->server;

@@ -111,11 +111,28 @@ struct SideEvolution {
 };
 
 // One pairwise contraction step (supplement, Eq. for C^{i_1..i_m}).
+// Store layout of a GEMM whose result goes straight into the order the next
+// step multiplies in (that step's boundary permute fused into the store):
+// complex element (m, n) of a unit lands at fa[m >> shift] + fb[m & mask] +
+// fg[n].  A pure axis permutation is additive over the digits of m and n, and
+// with power-of-two dimensions over the high and low bits of m, so three
+// small tables describe it exactly.
+struct ScatterStore {
+    const int64_t *fa = nullptr, *fb = nullptr, *fg = nullptr;
+    int shift = 0;
+    int mfast = 0;   // 1: consecutive rows are consecutive in the target, 0: columns
+};
+
 struct Step {
     int site = -1;                       // tensor absorbed (i_{m+1}); for step 0 the start
     std::vector<int> t_legs;             // boundary legs before the step (storage order)
     bool permute = false;
+    bool permute_fused = false;          // done by the previous step's GEMM store
     Gather perm;                         // boundary permute (t_legs -> m_legs ++ k_legs)
+    bool store_fused = false;            // this step's GEMM stores in the next step's order
+    std::vector<int64_t> sc_tab;         // host tables fa ++ fb ++ fg
+    int64_t sc_na = 0, sc_nb = 0;        // entries of fa and fb (fg: N entries)
+    int sc_shift = 0, sc_mfast = 0;
     std::vector<int> m_legs, k_legs, n_legs;
     int64_t M = 1, K = 1, N = 1;
     int kernel = 0;                      // 0 MFMA GEMM, 1 small, 2 final dot
@@ -221,6 +238,8 @@ struct Plan {
     DeviceBuf d_mats, d_chain, d_chain_off, d_chain_len, d_fuse, d_pq;
     DeviceBuf d_ket_vec, d_bra_mat;
     std::vector<DeviceBuf> ket_site;     // resident ket tensors (complex128)
+    std::vector<DeviceBuf> d_scatter;    // per step: fused-store tables (empty if none)
+    std::vector<ScatterStore> scatter;   // per step: device view of d_scatter
     int64_t resident_bytes = 0;
     int64_t bytes_per_unit = 0;
     int64_t bytes_per_bitstring = 0;
@@ -312,8 +331,11 @@ void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t
 void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
              int64_t slice0, int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream);
+// sc: when non-null, C is stored through the fused-store tables (the row
+// index includes every row of the unit, C is the unit's base)
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
-          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream);
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
+          const ScatterStore *sc = nullptr);
 void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
                     int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
                     void *stream);

@@ -258,6 +258,65 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
     if (NSPLIT == 3) *reinterpret_cast<bf16x4 *>(dst + 2 * part_stride) = l;
 }
 
+// Fused store of one wave's tile (WR rows, BJ slices of CW complex columns),
+// staged through LDS: stage(j) writes slice j into stg (row stride SLD
+// reals), then each lane stores whole complex values V in the order in
+// which the target is contiguous.  64 is a multiple of WR and of CW, so a
+// lane keeps one row (row order) or one column (column order) across its
+// stores, and the table lookups of that index are made once.
+template <typename V, int WR, int CW, int SLD, int BJ, typename R, typename Stage>
+__device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, const ScatterStore &sc,
+                                                 int64_t row0, int64_t rbase, int64_t M, int cbase0,
+                                                 int Nr, int lane, Stage stage) {
+    static_assert(64 % WR == 0 && 64 % CW == 0, "lane-invariant row or column");
+    constexpr int PER = WR * CW / 64;   // stores per lane and slice
+    const int64_t mask = ((int64_t)1 << sc.shift) - 1;
+    auto rowofs = [&](int lr) -> int64_t {
+        const int64_t row = rbase + lr;
+        if (row >= M) return -1;
+        const int64_t gr = row0 + row;
+        return sc.fa[gr >> sc.shift] + sc.fb[gr & mask];
+    };
+    if (sc.mfast) {
+        const int lr = lane % WR;
+        const int64_t ro = rowofs(lr);
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+            stage(j);
+            __syncthreads();
+            const int cb = cbase0 + j * 2 * CW;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int lc = lane / WR + k * (64 / WR);
+                const int col = cb + 2 * lc;
+                if (ro >= 0 && col < Nr)
+                    *reinterpret_cast<V *>(C + 2 * (ro + sc.fg[col >> 1])) =
+                        *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
+            }
+            __syncthreads();
+        }
+    } else {
+        const int lc = lane % CW;
+        int64_t ro[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) ro[k] = rowofs(lane / CW + k * (64 / CW));
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+            stage(j);
+            __syncthreads();
+            const int col = cbase0 + j * 2 * CW + 2 * lc;
+            const int64_t co = col < Nr ? sc.fg[col >> 1] : -1;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int lr = lane / CW + k * (64 / CW);
+                if (ro[k] >= 0 && co >= 0)
+                    *reinterpret_cast<V *>(C + 2 * (ro[k] + co)) = *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // C[M][Nr] = A[M][Kr] * Bt[Nr][Kr]^T, row-major, Kr % 4 == 0.  256 threads =
 // 4 waves in a WGM x WGN layout; each wave owns BI x BJ blocks of 32 x 32, so
 // the tile is (WGM*BI*32) x (WGN*BJ*32), k-step BK reals.  The next k-tile is
@@ -271,11 +330,15 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
 // 8-wide k group, so each lane reads its values with one 16-byte LDS load.
 // MODE 2 / 3: split-BF16 with 3 / 6 products, v_mfma_f32_32x32x16_bf16, a
 // lane supplying 8 consecutive k of its row (A) and of its column (B).
-template <int BI, int BJ, int WGM, int WGN, int MODE, int NSTAGE, int BK>
+// SCAT: the result is stored through fused-store tables (ScatterStore): the
+// complex element (row0 + row, col / 2) of the unit goes to
+// fa[r >> shift] + fb[r & mask] + fg[col / 2], the next step's order.
+template <int BI, int BJ, int WGM, int WGN, int MODE, int NSTAGE, int BK, bool SCAT>
 __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                                                    const float *__restrict__ Bt,
                                                    float *__restrict__ C, int64_t M, int Kr, int Nr,
-                                                   int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+                                                   int64_t sA, int64_t sB, int64_t sC, int tiles_n,
+                                                   ScatterStore sc, int64_t row0) {
     static_assert(WGM * WGN == 4, "four waves");
     constexpr int BM = WGM * BI * 32, BN = WGN * BJ * 32;
     constexpr int NSPLIT = MODE == 1 ? 1 : MODE;          // 1, 2 or 3 parts
@@ -416,16 +479,37 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     }
     // 32x32 accumulator layout: lane holds column lane%32 and rows
     // 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r.
+    if constexpr (!SCAT) {
 #pragma unroll
-    for (int i = 0; i < BI; ++i)
+        for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j)
+            for (int j = 0; j < BJ; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int col = n0 + wn * BJ * 32 + j * 32 + (lane & 31);
-                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
-            }
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int col = n0 + wn * BJ * 32 + j * 32 + (lane & 31);
+                    if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+                }
+    } else {
+        // Fused store, staged per wave through LDS (the A stages are free
+        // after the k-loop's last barrier): each 32-column slice of the
+        // wave's tile is written in the accumulator layout and read back one
+        // complex value per lane in the order in which the target is
+        // contiguous (rows when sc.mfast, else columns).
+        constexpr int WR = BI * 32;   // rows of the wave's tile
+        constexpr int CW = 16;        // complex columns of a slice
+        constexpr int SLD = 34;       // staging row: 32 floats + 2 (keeps float2 alignment)
+        static_assert(4 * WR * SLD * sizeof(float) <= sizeof(As), "staging fits in the A stages");
+        float *stg = reinterpret_cast<float *>(&As[0][0]) + wave * WR * SLD;
+        fused_store_wave<float2, WR, CW, SLD, BJ>(
+            C, stg, sc, row0, m0 + wm * WR, M, n0 + wn * BJ * 32, Nr, lane, [&](int j) {
+#pragma unroll
+                for (int i = 0; i < BI; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        stg[(i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + (lane & 31)] = acc[i][j][r];
+            });
+    }
 }
 
 // FP64 MFMA GEMM with v_mfma_f64_16x16x4f64: four waves in 2 x 2, each
@@ -436,12 +520,12 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 // (one barrier per k-step) as in the FP32 kernel.
 constexpr int F64_BK = 16, F64_LD = F64_BK + 2;
 
-template <int BI, int BJ, int NSTAGE>
+template <int BI, int BJ, int NSTAGE, bool SCAT>
 __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
                                                    const double *__restrict__ Bt,
                                                    double *__restrict__ C, int64_t M, int Kr,
                                                    int Nr, int64_t sA, int64_t sB, int64_t sC,
-                                                   int tiles_n) {
+                                                   int tiles_n, ScatterStore sc, int64_t row0) {
     constexpr int BM = 32 * BI, BN = 32 * BJ;
     constexpr int AP = BM / 64, BP = BN / 64;   // 64-row load passes per operand
     static_assert(BM % 64 == 0 && BN % 64 == 0, "tile edges are multiples of 64");
@@ -535,16 +619,43 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
         }
     }
     // 16x16 f64 accumulator layout: lane holds column lane%16 and rows lane/16 + 4*r.
+    if constexpr (!SCAT) {
 #pragma unroll
-    for (int i = 0; i < BI; ++i)
+        for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j)
+            for (int j = 0; j < BJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * BI * 16 + i * 16 + (lane >> 4) + 4 * r;
+                    const int col = n0 + wn * BJ * 16 + j * 16 + (lane & 15);
+                    if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+                }
+    } else {
+        // fused store, direct: each lane already writes 8-byte values and the
+        // re/im halves of a complex value sit in neighbouring lanes, so
+        // (measured) staging through LDS does not pay here; the row parts of
+        // the target offsets are looked up once per row, the column parts
+        // once per column block
+        int64_t cofs[BJ];
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+            const int col = n0 + wn * BJ * 16 + j * 16 + (lane & 15);
+            cofs[j] = col < Nr ? 2 * sc.fg[col >> 1] + (col & 1) : -1;
+        }
+        const int64_t mask = ((int64_t)1 << sc.shift) - 1;
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm * BI * 16 + i * 16 + (lane >> 4) + 4 * r;
-                const int col = n0 + wn * BJ * 16 + j * 16 + (lane & 15);
-                if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
+                if (row >= M) continue;
+                const int64_t gr = row0 + row;
+                const int64_t rofs = 2 * (sc.fa[gr >> sc.shift] + sc.fb[gr & mask]);
+#pragma unroll
+                for (int j = 0; j < BJ; ++j)
+                    if (cofs[j] >= 0) C[rofs + cofs[j]] = acc[i][j][r];
             }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -703,7 +814,40 @@ void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
         check_launch("permute");
         return;
     }
-    if (per < ((int64_t)1 << 31) && units <= 65535) {
+    constexpr int64_t k31 = (int64_t)1 << 31;
+    if (per >= k31 && g.n >= 2) {
+        // Peel leading output axes until one launch covers < 2^31 elements:
+        // the last peeled axis becomes the launch's unit dimension, the ones
+        // before it and the units are host loops; each piece then takes the
+        // 32-bit kernel below.
+        int p = 0;
+        int64_t rest = per;
+        while (p < g.n - 1 && rest >= k31) rest /= g.size[p++];
+        if (rest < k31 && g.size[p - 1] <= 65535) {
+            Gather inner{};
+            inner.n = g.n - p;
+            for (int a = p; a < g.n; ++a) {
+                inner.size[a - p] = g.size[a];
+                inner.stride[a - p] = g.stride[a];
+            }
+            int64_t outer = 1;
+            for (int a = 0; a < p - 1; ++a) outer *= g.size[a];
+            const int64_t lead = g.size[p - 1];
+            for (int64_t u = 0; u < units; ++u)
+                for (int64_t o = 0; o < outer; ++o) {
+                    int64_t in_off = u * in_unit_stride, r = o;
+                    for (int a = p - 2; a >= 0; --a) {
+                        in_off += (r % g.size[a]) * g.stride[a];
+                        r /= g.size[a];
+                    }
+                    const int64_t out_off = u * out_unit_stride + o * lead * rest;
+                    gather((const char *)in + in_off * elem_bytes, (char *)out + out_off * elem_bytes,
+                           lead, g.stride[p - 1], rest, inner, elem_bytes, stream);
+                }
+            return;
+        }
+    }
+    if (per < k31 && units <= 65535) {
         const bool vec = elem_bytes == 8 && g.stride[g.n - 1] == 1 && g.size[g.n - 1] % 2 == 0;
         const int64_t work = vec ? per / 2 : per;
         const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 1023) / 1024, 65536));
@@ -770,20 +914,45 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
 // NSTAGE: two LDS stages on the 128 x 128 tile (k-step 32: 73.7 KB FP32,
 // 81.9 KB 3-product BF16; the 6-product form takes k-step 16, 61.4 KB), so
 // two blocks fit on a CU; one stage on the narrow tiles.
-template <int BI, int BJ, int WGM, int WGN>
+template <int BI, int BJ, int WGM, int WGN, bool SCAT>
 static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
-                       int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+                       int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n,
+                       const ScatterStore &sc, int64_t row0) {
     constexpr int S = WGN == 2 ? 2 : 1;
     if (mode == 1)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
+                           sA, sB, sC, tiles_n, sc, row0);
     else if (mode == 2)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 32>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
+                           sA, sB, sC, tiles_n, sc, row0);
     else
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, S, (S == 2 ? 16 : 32)>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n);
+        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, S, (S == 2 ? 16 : 32), SCAT>), grid, dim3(256), 0, st, A,
+                           B, C, M, Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+}
+
+template <int BI, int BJ, int WGM, int WGN>
+static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
+                       int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n,
+                       const ScatterStore *sc, int64_t row0) {
+    if (sc) launch_c64<BI, BJ, WGM, WGN, true>(mode, grid, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n, *sc, row0);
+    else launch_c64<BI, BJ, WGM, WGN, false>(mode, grid, st, A, B, C, M, Kr, Nr, sA, sB, sC, tiles_n, ScatterStore{}, 0);
+}
+
+template <int BI, int BJ>
+static void launch_f64(dim3 grid, hipStream_t st, const double *A, const double *B, double *C, int64_t M, int Kr,
+                       int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n, const ScatterStore *sc,
+                       int64_t row0) {
+    if (sc)
+        hipLaunchKernelGGL((k_gemm_f64<BI, BJ, 2, true>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC,
+                           tiles_n, *sc, row0);
+    else
+        hipLaunchKernelGGL((k_gemm_f64<BI, BJ, 2, false>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr, sA, sB, sC,
+                           tiles_n, ScatterStore{}, (int64_t)0);
 }
 
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
-          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream) {
+          int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
+          const ScatterStore *sc) {
     // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
     // split-BF16 MFMA with 3 / 6 products.  Strides arrive in complex elements;
     // the kernels index reals.
@@ -808,23 +977,21 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
             const int64_t mr = std::min<int64_t>(rows_per, M - r0);
             const int64_t tiles_m = (mr + BM - 1) / BM;
             const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)nu);
+            // with a fused store the row offset goes to the tables, not to C
+            const int64_t crow = sc ? 0 : r0;
             if (c64) {
                 const float *a = (const float *)A + 2 * (u0 * sA + r0 * K);
                 const float *b = (const float *)Bt + 4 * u0 * sB;
-                float *c = (float *)C + 2 * (u0 * sC + r0 * N);
-                if (shape == 1) launch_c64<2, 1, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
-                else if (shape == 2) launch_c64<2, 2, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
-                else launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n);
+                float *c = (float *)C + 2 * (u0 * sC + crow * N);
+                if (shape == 1) launch_c64<2, 1, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
+                else if (shape == 2) launch_c64<2, 2, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
+                else launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
             } else {
                 const double *a = (const double *)A + 2 * (u0 * sA + r0 * K);
                 const double *b = (const double *)Bt + 4 * u0 * sB;
-                double *c = (double *)C + 2 * (u0 * sC + r0 * N);
-                if (shape == 4)
-                    hipLaunchKernelGGL((k_gemm_f64<4, 4, 2>), grid, dim3(256), 0, st, a, b, c, mr, Kr, Nr,
-                                       2 * sA, 4 * sB, 2 * sC, tiles_n);
-                else
-                    hipLaunchKernelGGL((k_gemm_f64<2, 2, 2>), grid, dim3(256), 0, st, a, b, c, mr, Kr, Nr,
-                                       2 * sA, 4 * sB, 2 * sC, tiles_n);
+                double *c = (double *)C + 2 * (u0 * sC + crow * N);
+                if (shape == 4) launch_f64<4, 4>(grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
+                else launch_f64<2, 2>(grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
             }
             check_launch("gemm");
         }

@@ -593,6 +593,85 @@ Gather compact(const std::vector<int64_t> &size, const std::vector<int64_t> &str
     return g;
 }
 
+// Fused-store tables (ScatterStore) of a GEMM step whose product, in its
+// natural [M][N] order, the next step permutes with `g` (target axes with
+// their natural strides).  Every target axis is a digit field of m or of n (an
+// axis straddling the boundary is split in two); with power-of-two sizes the
+// digit fields are bit fields, so f(m) = fa[m >> shift] + fb[m & mask] is
+// exact.  Returns false where the tables do not apply.
+bool build_scatter(const Gather &g, int64_t M, int64_t N, Step &s) {
+    auto pow2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
+    if (!pow2(M) || !pow2(N)) return false;
+    std::vector<int64_t> ts(g.n);
+    int64_t t = 1;
+    for (int a = g.n - 1; a >= 0; --a) { ts[a] = t; t *= g.size[a]; }
+    if (t != M * N) return false;
+    struct Ax { int64_t stride, size, ts; };
+    std::vector<Ax> am, an;   // digit fields of m (strides in rows) and of n
+    for (int a = 0; a < g.n; ++a) {
+        const int64_t st = g.stride[a], z = g.size[a];
+        if (z == 1) continue;
+        if (!pow2(z) || !pow2(st)) return false;
+        if (st >= N) am.push_back({st / N, z, ts[a]});
+        else if (st * z <= N) an.push_back({st, z, ts[a]});
+        else {
+            const int64_t zl = N / st;
+            an.push_back({st, zl, ts[a]});
+            am.push_back({1, z / zl, ts[a] * zl});
+        }
+    }
+    auto f = [](const std::vector<Ax> &ax, int64_t x) {
+        int64_t y = 0;
+        for (const Ax &a : ax) y += ((x / a.stride) % a.size) * a.ts;
+        return y;
+    };
+    int lg = 0;
+    while (((int64_t)1 << lg) < M) ++lg;
+    const int shift = lg / 2;
+    const int64_t na = M >> shift, nb = (int64_t)1 << shift;
+    if (na + nb + N > ((int64_t)1 << 23)) return false;
+    s.sc_tab.resize(na + nb + N);
+    for (int64_t h = 0; h < na; ++h) s.sc_tab[h] = f(am, h << shift);
+    for (int64_t l = 0; l < nb; ++l) s.sc_tab[na + l] = f(am, l);
+    for (int64_t n = 0; n < N; ++n) s.sc_tab[na + nb + n] = f(an, n);
+    // Self-check.  Bounds: the largest entries add up to less than M*N, so
+    // no store can leave the unit.  Semantics: decoding f(m) + g(n) over the
+    // target axes must lead back to the natural index m*N + n (every pair
+    // when M*N <= 2^16, else 4096 pairs and the corners).
+    const int64_t *fa = s.sc_tab.data(), *fb = fa + na, *fg = fb + nb;
+    const int64_t ma = *std::max_element(fa, fa + na), mb = *std::max_element(fb, fb + nb),
+                  mg = *std::max_element(fg, fg + N);
+    if (ma + mb + mg >= M * N) fail(TNS_E_BAD_PATH, "internal: fused store leaves the tensor");
+    auto back = [&](int64_t m, int64_t n) {
+        int64_t r = fa[m >> shift] + fb[m & (nb - 1)] + fg[n], x = 0;
+        for (int a = g.n - 1; a >= 0; --a) {
+            x += (r % g.size[a]) * g.stride[a];
+            r /= g.size[a];
+        }
+        return x == m * N + n;
+    };
+    bool ok = back(0, 0) && back(M - 1, N - 1);
+    if (M * N <= ((int64_t)1 << 16)) {
+        for (int64_t m = 0; m < M && ok; ++m)
+            for (int64_t n = 0; n < N && ok; ++n) ok = back(m, n);
+    } else {
+        uint64_t x = 0x9e3779b97f4a7c15ull;
+        for (int i = 0; i < 4096 && ok; ++i) {
+            x = x * 6364136223846793005ull + 1442695040888963407ull;
+            ok = back((int64_t)((x >> 20) % (uint64_t)M), (int64_t)((x >> 8) % (uint64_t)N));
+        }
+    }
+    if (!ok) fail(TNS_E_BAD_PATH, "internal: fused store tables disagree with the permute");
+    s.sc_na = na;
+    s.sc_nb = nb;
+    s.sc_shift = shift;
+    // store order: columns when the new legs stay fastest, else rows when
+    // row m+1 follows row m in the target
+    const int64_t f1 = M > 1 ? (nb > 1 ? fb[1] : fa[1]) : -1;
+    s.sc_mfast = (N > 1 && fg[1] == 1) ? 0 : (f1 == 1 ? 1 : 0);
+    return true;
+}
+
 }  // namespace
 
 static void compile_steps(Plan &p) {
@@ -724,6 +803,16 @@ static void compile_steps(Plan &p) {
         p.flops_per_amp += 8.0 * mkn;
         p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
         p.steps.push_back(s);
+    }
+    // a boundary permute after a GEMM step goes into that GEMM's store
+    for (size_t m = 2; m < p.steps.size(); ++m) {
+        Step &s = p.steps[m], &prev = p.steps[m - 1];
+        if (!s.permute || prev.kernel != 0) continue;
+        if (build_scatter(s.perm, prev.M, prev.N, prev)) {
+            s.permute_fused = true;
+            prev.store_fused = true;
+            p.permute_bytes_per_amp -= 2.0 * elem * (double)(prev.M * prev.N);
+        }
     }
     // open legs of the last tensor -> output order (first open qubit most significant)
     p.out_per_unit = (int64_t)1 << c.n_open;
@@ -1131,7 +1220,7 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
         p.info_k.push_back(p.steps[i].K);
         p.info_n.push_back(p.steps[i].N);
         p.info_kernel.push_back(p.steps[i].kernel);
-        p.info_permute.push_back(p.steps[i].permute ? 1 : 0);
+        p.info_permute.push_back(!p.steps[i].permute ? 0 : (p.steps[i].permute_fused ? 2 : 1));
     }
     const int elem = p.precision == TNS_C128 ? 16 : 8;
     // one unit: two boundary buffers, the B operand (embedded form is 2x) and the partial

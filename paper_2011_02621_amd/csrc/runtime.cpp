@@ -175,6 +175,17 @@ void plan_device_setup(Ctx *ctx, Plan &p) {
     dev_free(ctx, bc.ptr, st);
 
     p.resident_bytes += p.d_mats.bytes + p.d_pq.bytes + p.d_fuse.bytes + p.d_chain.bytes;
+    // fused-store tables of the GEMM steps that write in the next step's order
+    p.d_scatter.assign(p.steps.size(), DeviceBuf{});
+    p.scatter.assign(p.steps.size(), ScatterStore{});
+    for (size_t m = 0; m < p.steps.size(); ++m) {
+        const Step &s = p.steps[m];
+        if (!s.store_fused) continue;
+        p.d_scatter[m] = upload(ctx, s.sc_tab.data(), s.sc_tab.size() * sizeof(int64_t), st);
+        const int64_t *t = (const int64_t *)p.d_scatter[m].ptr;
+        p.scatter[m] = ScatterStore{t, t + s.sc_na, t + s.sc_na + s.sc_nb, s.sc_shift, s.sc_mfast};
+        p.resident_bytes += p.d_scatter[m].bytes;
+    }
     hip_check(hipStreamSynchronize((hipStream_t)st), "plan upload");
     p.ctx = ctx;
     p.on_device = true;
@@ -192,6 +203,9 @@ void plan_device_release(Plan &p) {
     }
     for (auto &b : p.ket_site) dev_free(ctx, b.ptr, st);
     p.ket_site.clear();
+    for (auto &b : p.d_scatter) dev_free(ctx, b.ptr, st);
+    p.d_scatter.clear();
+    p.scatter.clear();
     p.on_device = false;
 }
 
@@ -344,7 +358,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 const Step &s = p.steps[m];
                 char *src = cur;
                 char *other = (cur == X) ? Y : X;
-                if (s.permute) {
+                if (s.permute && !s.permute_fused) {
                     int64_t te = 1;
                     for (int a = 0; a < s.perm.n; ++a) te *= s.perm.size[a];
                     ev_begin(1, 0, 2.0 * elem * te * g);
@@ -361,7 +375,8 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 const double by = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
                 ev_begin(s.kernel == 0 ? 0 : 2, 8.0 * mkn, by);
                 if (s.kernel == 0)
-                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream);
+                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream,
+                                 s.store_fused ? &p.scatter[m] : nullptr);
                 else if (s.kernel == 1)
                     launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
                                            c64 ? 1 : 0, stream);
