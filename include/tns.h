@@ -118,8 +118,10 @@ typedef struct {
     const int32_t *cut_edges;  /* [n_cuts] edge ids to slice over */
     uint64_t max_intermediate_elems; /* automatic cuts keep every intermediate at or
                                         below this many elements; 0 = 2^32 */
-    double svd_rel_cutoff;     /* singular values <= cutoff * sigma_max count as zero
-                                  when reporting numerical ranks; 0 = 1e-12 */
+    double svd_rel_cutoff;     /* in every SVD compression (Eq. (5)), singular values
+                                  <= cutoff * sigma_max of that SVD are set to zero
+                                  (the planned bond dimension is kept, the dropped
+                                  directions carry exact zeros); 0 = 1e-12 */
     int64_t max_search_states; /* Algorithm 1 pop budget; 0 = 4,000,000 */
     tns_precision precision;
     int32_t n_open;            /* 0..20 qubits whose output bit is left open */

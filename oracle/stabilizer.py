@@ -127,6 +127,45 @@ class Tableau:
         return out
 
 
+def support_sample(tab: Tableau, count: int, seed: int) -> np.ndarray:
+    """Uniform bitstrings from the support of the state: the s with nonzero
+    amplitude solve z . s = (e / 2) mod 2 for every Z-type stabilizer
+    (e, z), an affine subspace of GF(2)^N.  Gauss-Jordan elimination gives
+    a particular solution and a null-space basis; each sample adds a random
+    combination of the basis (numpy default_rng(seed))."""
+    _, ztype = tab.z_subgroup()
+    n = tab.n
+    rows = [(zz.astype(np.uint8).copy(), (e // 2) % 2) for e, zz in ztype]
+    a = np.array([r[0] for r in rows], np.uint8).reshape(-1, n)
+    b = np.array([r[1] for r in rows], np.uint8)
+    pivots, r = [], 0
+    for col in range(n):
+        hit = [i for i in range(r, a.shape[0]) if a[i, col]]
+        if not hit:
+            continue
+        i = hit[0]
+        a[[r, i]] = a[[i, r]]
+        b[[r, i]] = b[[i, r]]
+        for j in range(a.shape[0]):
+            if j != r and a[j, col]:
+                a[j] ^= a[r]
+                b[j] ^= b[r]
+        pivots.append(col)
+        r += 1
+    if np.any(b[r:]):
+        raise AssertionError("inconsistent Z-type stabilizers")
+    free = [c for c in range(n) if c not in pivots]
+    rng = np.random.default_rng(seed)
+    out = np.zeros((count, n), np.uint8)
+    for t in range(count):
+        s = np.zeros(n, np.uint8)
+        s[free] = rng.integers(0, 2, len(free))
+        for i, col in enumerate(pivots):
+            s[col] = (b[i] + int(np.dot(a[i, free].astype(np.int64), s[free]))) % 2
+        out[t] = s
+    return out
+
+
 def run(circ) -> Tableau:
     """Evolve |0^N> through a Clifford circuit."""
     tab = Tableau(circ.n)

@@ -316,7 +316,7 @@ void gate_apply(const double *in, double *out, int64_t nb, int64_t in_stride,
                 void *stream);
 void svd_compress(const double *in, double *out_site, double *vp, int64_t nb,
                   int64_t in_stride, int64_t out_stride, int64_t vp_stride, SiteShape s,
-                  int leg, void *stream);
+                  int leg, double cutoff, void *stream);
 void absorb(const double *in, const double *vp, double *out, int64_t nb, int64_t in_stride,
             int64_t vp_stride, int64_t out_stride, SiteShape s, int leg, int r,
             void *stream);

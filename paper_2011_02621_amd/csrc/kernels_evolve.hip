@@ -4,7 +4,8 @@
 //   gate_apply   -- P or Q applied to one site, widening one bond by chi
 //                   (Eqs. (3)-(4))
 //   svd_compress -- one-sided Jacobi SVD of the widened site, keeping the
-//                   planned rank (Eq. (5))
+//                   planned rank (Eq. (5)); singular values below the
+//                   relative cutoff are set to zero
 //   absorb       -- S V folded into the neighbouring site (Eq. (6))
 //   merge        -- overlap site tensors C = sum_sigma A^sigma B^sigma (Eq. (8))
 #include <hip/hip_runtime.h>
@@ -37,11 +38,22 @@ struct Rot {
     double c, s;
     cdbl ph;   // e^{i phi}
 };
+// floor: rows whose squared norm is at or below it count as zero and are not
+// rotated.  Rows left over from exact cancellations can be as small as
+// 1e-150 of the matrix scale; their Gram entries are then denormal, the
+// phase gamma / |gamma| loses its unit modulus and the rotation stops being
+// unitary, which breaks the factorisation A = J W the compression relies on.
+// Not rotating such a pair is the identity, which is always exact.  The
+// threshold is formed as sqrt(alpha) sqrt(beta) (alpha * beta can underflow)
+// and the phase is renormalised.
 __device__ __forceinline__ bool make_rot(double alpha, double beta, cdbl gamma, double tol,
-                                         Rot &r) {
+                                         double floor, Rot &r) {
+    if (!(alpha > floor) || !(beta > floor)) return false;
     double g = sqrt(gamma.x * gamma.x + gamma.y * gamma.y);
-    if (!(alpha > 0.0) || !(beta > 0.0) || g <= tol * sqrt(alpha * beta)) return false;
+    if (!(g > tol * sqrt(alpha) * sqrt(beta))) return false;
     r.ph = {gamma.x / g, gamma.y / g};
+    const double pn = sqrt(r.ph.x * r.ph.x + r.ph.y * r.ph.y);
+    r.ph = {r.ph.x / pn, r.ph.y / pn};
     double zeta = (beta - alpha) / (2.0 * g);
     double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     r.c = 1.0 / sqrt(1.0 + t * t);
@@ -65,6 +77,9 @@ __device__ __forceinline__ void rot_cols(cdbl &jp, cdbl &jq, const Rot &r) {
 
 constexpr double kJacobiTol = 1e-14;
 constexpr int kMaxSweeps = 40;
+// zero-row floor of the Jacobi rotations, relative to the largest squared
+// row norm of the matrix, with an absolute floor above the denormal range
+__device__ __forceinline__ double jacobi_floor(double max_row2) { return fmax(1e-200 * max_row2, 1e-290); }
 
 // ---------------------------------------------------------------------------
 // fuse + split: one thread per fused gate, one per qubit boundary chain
@@ -147,6 +162,13 @@ __global__ void k_fuse_split(const double *__restrict__ mats, const int32_t *cha
                     W[2 * a0p + a0][2 * b0p + b0] = F[2 * a0p + b0p][2 * a0 + b0];
     for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c) J[r][c] = {r == c ? 1.0 : 0.0, 0.0};
+    double max_row2 = 0;
+    for (int r = 0; r < 4; ++r) {
+        double a = 0;
+        for (int c = 0; c < 4; ++c) a += W[r][c].x * W[r][c].x + W[r][c].y * W[r][c].y;
+        max_row2 = fmax(max_row2, a);
+    }
+    const double floor4 = jacobi_floor(max_row2);
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         bool changed = false;
         for (int p = 0; p < 4; ++p)
@@ -159,7 +181,7 @@ __global__ void k_fuse_split(const double *__restrict__ mats, const int32_t *cha
                     ga = cadd(ga, cmul(W[p][c], cconj(W[q][c])));
                 }
                 Rot r;
-                if (!make_rot(al, be, ga, kJacobiTol, r)) continue;
+                if (!make_rot(al, be, ga, kJacobiTol, floor4, r)) continue;
                 changed = true;
                 for (int c = 0; c < 4; ++c) rot_rows(W[p][c], W[q][c], r);
                 for (int c = 0; c < 4; ++c) rot_cols(J[c][p], J[c][q], r);
@@ -275,9 +297,12 @@ __global__ void k_gate_apply(const double *__restrict__ in, double *__restrict__
 
 constexpr int kSvdThreads = 256;
 
+// cut2: a kept row of S V whose squared norm is at most cut2 times the
+// largest is written as exact zeros (a singular value below the relative
+// cutoff counts as zero; the planned shape is unchanged)
 __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
     const double *__restrict__ in, double *__restrict__ out_site, double *__restrict__ vp,
-    int64_t in_stride, int64_t out_stride, int64_t vp_stride, LegSplit ls, int R) {
+    int64_t in_stride, int64_t out_stride, int64_t vp_stride, LegSplit ls, int R, double cut2) {
     extern __shared__ double lds[];
     const int C = (int)ls.D;
     cdbl *W = reinterpret_cast<cdbl *>(lds);          // [R][C]
@@ -285,6 +310,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
     double *nrm = reinterpret_cast<double *>(J + (int64_t)R * R);   // [R]
     int *perm = reinterpret_cast<int *>(nrm + R);      // [R]
     __shared__ int changed;
+    __shared__ double wmax[kSvdThreads / 64];
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
     const double *src = in + 2 * b * in_stride;
@@ -297,6 +323,20 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
     }
     for (int e = tid; e < R * R; e += kSvdThreads) J[e] = {(e / R) == (e % R) ? 1.0 : 0.0, 0.0};
     __syncthreads();
+    // largest squared row norm: the scale of the zero-row floor
+    double mx0 = 0;
+    for (int s = tid; s < R; s += kSvdThreads) {
+        double a = 0;
+        for (int c = 0; c < C; ++c) a += W[s * C + c].x * W[s * C + c].x + W[s * C + c].y * W[s * C + c].y;
+        mx0 = fmax(mx0, a);
+    }
+    for (int m = 32; m > 0; m >>= 1) mx0 = fmax(mx0, __shfl_xor(mx0, m, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = mx0;
+    __syncthreads();
+    double scale0 = 0;
+    for (int w = 0; w < kSvdThreads / 64; ++w) scale0 = fmax(scale0, wmax[w]);
+    const double zfloor = jacobi_floor(scale0);
+    __syncthreads();   // wmax is reused below
 
     const int Rp = R + (R & 1);
     const int npairs = Rp / 2;
@@ -333,7 +373,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
                 ga.y += __shfl_xor(ga.y, m, 64);
             }
             Rot r;
-            if (active && make_rot(al, be, ga, kJacobiTol, r)) {
+            if (active && make_rot(al, be, ga, kJacobiTol, zfloor, r)) {
                 for (int c = gl; c < C; c += G) rot_rows(W[p * C + c], W[q * C + c], r);
                 for (int rr = gl; rr < R; rr += G) rot_cols(J[rr * R + p], J[rr * R + q], r);
                 if (gl == 0) changed = 1;
@@ -344,12 +384,19 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
         __syncthreads();
     }
     // singular values and their descending order
+    double mx = 0;
     for (int s = tid; s < R; s += kSvdThreads) {
         double a = 0;
         for (int c = 0; c < C; ++c) a += W[s * C + c].x * W[s * C + c].x + W[s * C + c].y * W[s * C + c].y;
         nrm[s] = a;
+        mx = fmax(mx, a);
     }
+    for (int m = 32; m > 0; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = mx;
     __syncthreads();
+    double smax = 0;
+    for (int w = 0; w < kSvdThreads / 64; ++w) smax = fmax(smax, wmax[w]);
+    const double zero_below = cut2 * smax;
     for (int s = tid; s < R; s += kSvdThreads) {
         int rank = 0;
         for (int t = 0; t < R; ++t) rank += (nrm[t] > nrm[s]) || (nrm[t] == nrm[s] && t < s);
@@ -368,7 +415,8 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_rows(
     double *vd = vp + 2 * b * vp_stride;
     for (int e = tid; e < R * C; e += kSvdThreads) {
         const int sp = e / C, c = e % C;
-        cdbl v = W[perm[sp] * C + c];
+        const bool zero = nrm[perm[sp]] <= zero_below;
+        cdbl v = zero ? cdbl{0.0, 0.0} : W[perm[sp] * C + c];
         vd[2 * e] = v.x;
         vd[2 * e + 1] = v.y;
     }
@@ -498,7 +546,7 @@ size_t svd_lds_bytes(int R, int C) {
 
 void svd_compress(const double *in, double *out_site, double *vp, int64_t nb,
                   int64_t in_stride, int64_t out_stride, int64_t vp_stride, SiteShape s,
-                  int leg, void *stream) {
+                  int leg, double cutoff, void *stream) {
     LegSplit ls = leg_split(s, leg);
     const int64_t rows = 2 * ls.outer * ls.inner;
     const size_t lds = svd_lds_bytes((int)rows, (int)ls.D);
@@ -512,7 +560,7 @@ void svd_compress(const double *in, double *out_site, double *vp, int64_t nb,
     LegSplit rs = ls;
     rs.outer = 2 * ls.outer;
     hipLaunchKernelGGL(k_svd_rows, dim3((unsigned)nb), dim3(kSvdThreads), lds, (hipStream_t)stream,
-                       in, out_site, vp, in_stride, out_stride, vp_stride, rs, (int)rows);
+                       in, out_site, vp, in_stride, out_stride, vp_stride, rs, (int)rows, cutoff * cutoff);
     check_launch("svd_compress");
 }
 

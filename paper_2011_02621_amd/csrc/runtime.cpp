@@ -106,7 +106,8 @@ static void run_side(const Plan &p, const SideEvolution &side, SideBuffers &sb, 
         sk.d[1 + legk] = op.d_grown;
         sl.d[1 + legl] = op.d_grown;
         launch::svd_compress(sb.buf[sb.cur[k]][k], sb.buf[1 - sb.cur[k]][k], vp, nb, sb.stride[k],
-                             sb.stride[k], vp_stride, sk, legk, stream);
+                             sb.stride[k], vp_stride, sk, legk,
+                             p.opts.svd_rel_cutoff > 0 ? p.opts.svd_rel_cutoff : 1e-12, stream);
         sb.cur[k] ^= 1;
         launch::absorb(sb.buf[sb.cur[l]][l], vp, sb.buf[1 - sb.cur[l]][l], nb, sb.stride[l], vp_stride,
                        sb.stride[l], sl, legl, op.d_after, stream);

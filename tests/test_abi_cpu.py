@@ -128,6 +128,23 @@ def test_plan_info_consistency(ctx):
     assert s == pytest.approx(i.path_score) and peak == i.peak_elems
 
 
+def test_permutes_fused_into_gemm_stores(ctx):
+    # a boundary permute after an MFMA GEMM step is done by that GEMM's store
+    c, _ = config("grid5x5_d10")
+    for prec in ("c64", "c128"):
+        i = ctx.plan(c, precision=prec).info()
+        sp, k = np.asarray(i.step_permute), np.asarray(i.step_kernel)
+        assert (sp == 2).sum() > 0
+        for t in np.nonzero(sp == 2)[0]:
+            assert t >= 2 and k[t - 1] == 0
+        for t in np.nonzero(sp == 1)[0]:
+            assert t < 2 or k[t - 1] != 0
+        # permute launches only: bytes of the fused ones are not counted
+        elem = 16 if prec == "c128" else 8
+        launched = sum(2.0 * elem * i.step_m[t - 1] * i.step_n[t - 1] for t in np.nonzero(sp == 1)[0])
+        assert i.permute_bytes_per_amp == pytest.approx(launched * i.n_slices)
+
+
 def test_fidelity_reported(ctx):
     c, _ = config("diag53_d12", final_layer=False)
     i = ctx.plan(c, split_cycle=6, path_mode="greedy", max_intermediate_elems=1 << 60).info()

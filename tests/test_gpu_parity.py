@@ -202,6 +202,39 @@ def test_mirror_53(ctx):
     assert np.abs(got[1:]).max() < 1e-10
 
 
+@pytest.mark.parametrize("rows,cols,seed", [(2, 3, 8), (2, 3, 9), (3, 3, 9), (5, 5, 7)])
+def test_mirror_every_split(ctx, rows, cols, seed):
+    # Exactly cancelling gates (U then U^-1) leave rows of the compressed
+    # site matrices at ~1e-150 of their scale; the Jacobi rotations must stay
+    # unitary there.  Every split point, zero bitstring and random ones.
+    c = mirror_circuit(grid(rows, cols), 4, seed)
+    n = rows * cols
+    bits = np.vstack([np.zeros((1, n), np.uint8), bitstrings(n, 7, 5)])
+    say("mirror grid%dx%d seed %d, every split" % (rows, cols, seed))
+    for k in range(0, 9):
+        p = ctx.plan(c, precision="c128", split_cycle=k)
+        got = ctx.amplitudes(p, bits)
+        assert abs(got[0] - 1) < 1e-10, (k, got[0])
+        assert np.abs(got[1:]).max() < 1e-10, k
+        p.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_mirror_104(ctx, prec):
+    # 104 qubits, 4 + 4 cycles: 103 contraction steps, most of their boundary
+    # permutes done by the producing GEMM's store; <0|W|0> = 1 exactly and
+    # every other amplitude is 0
+    c = mirror_circuit(grid(8, 13), 4, 7)
+    bits = np.vstack([np.zeros((1, 104), np.uint8), bitstrings(104, 3, 9)])
+    say("mirror grid8x13 4+4", prec)
+    p = ctx.plan(c, precision=prec)
+    assert (np.asarray(p.info().step_permute) == 2).sum() > 50
+    got = ctx.amplitudes(p, bits)
+    tol = TOL[prec]
+    assert abs(got[0] - 1) < tol
+    assert np.abs(got[1:]).max() < tol
+
+
 def test_clifford_53_against_tableau(ctx):
     c = random_circuit(diagonal53(), 6, 13, clifford=True)
     bits = bitstrings(53, 8, 14)
@@ -209,6 +242,25 @@ def test_clifford_53_against_tableau(ctx):
     p_ref = stabilizer.probabilities(c, bits)
     got = ctx.amplitudes(ctx.plan(c, precision="c128"), bits)
     assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 1e-10 * max(p_ref.max(), 2.0 ** -53)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_clifford_104_against_tableau(ctx, prec):
+    # 104 qubits, 8 cycles: the same bond dimensions, path shape and 2^32-
+    # element intermediates as the random 8x13 workload, with exact
+    # probabilities from the tableau; two bitstrings from the state's support
+    # (|amp|^2 = 2^-rank) and one uniform one (almost surely outside it)
+    c = random_circuit(grid(8, 13), 8, 15, clifford=True)
+    tab = stabilizer.run(c)
+    bits = np.vstack([stabilizer.support_sample(tab, 2, 3), bitstrings(104, 1, 17)])
+    p_ref = tab.probabilities(bits)
+    assert p_ref[0] > 0 and p_ref[1] > 0
+    say("clifford grid8x13 d8", prec, "plan")
+    p = ctx.plan(c, precision=prec, split_cycle=1)
+    say("clifford grid8x13 d8", prec, "contract, %.2e flop/amp" % p.info().flops_per_amp)
+    got = ctx.amplitudes(p, bits)
+    tol = TOL[prec]
+    assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 2 * tol * max(p_ref.max(), 2.0 ** -104)
 
 
 def test_stream_argument(ctx, small):

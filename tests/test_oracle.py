@@ -179,3 +179,32 @@ def test_tableau_scales_to_53_qubits():
     if nz.size:
         assert np.allclose(nz, nz[0])
         assert float(np.log2(nz[0])).is_integer()
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed", [(3, 4, 8, 32), (3, 4, 5, 33), (2, 4, 6, 34)])
+def test_support_sample_against_state_vector(rows, cols, depth, seed):
+    # the sampler draws from the set the dense state vector says is nonzero,
+    # that set has 2^rank elements, and the samples cover it uniformly
+    c = random_circuit(grid(rows, cols), depth, seed, clifford=True)
+    n = c.n
+    tab = stabilizer.run(c)
+    rank, _ = tab.z_subgroup()
+    p_sv = np.abs(sv.amplitudes(c, all_bits(n))) ** 2
+    support = np.nonzero(p_sv > 1e-12)[0]
+    assert len(support) == 2 ** rank
+    s = stabilizer.support_sample(tab, 4000, 7)
+    idx = s.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
+    assert np.all(p_sv[idx] > 1e-12)
+    counts = np.bincount(idx, minlength=2 ** n)[support]
+    if len(support) <= 64:
+        # every element drawn, none wildly over-represented
+        assert counts.min() > 0 and counts.max() < 6 * 4000 / len(support)
+
+
+def test_support_sample_scales_to_104_qubits():
+    c = random_circuit(grid(8, 13), 8, 15, clifford=True)
+    tab = stabilizer.run(c)
+    s = stabilizer.support_sample(tab, 8, 3)
+    p = tab.probabilities(s)
+    rank, _ = tab.z_subgroup()
+    assert np.all(p == 2.0 ** -rank)
