@@ -240,6 +240,20 @@ def bench_53(T, ctx, args, torch):
             po.close()
         corr["c64_rel_l2_vs_c128"] = rel_l2(ca["c128"].reshape(-1), ca["c64"].reshape(-1))
         res["correlated_batch"] = corr
+        # frugal rejection sampling over correlated batches (M = 10)
+        ps = ctx.plan(c10, precision="c64", open_qubits=oq)
+        fixed = bitstrings(53, 8, 104)
+        u = np.random.default_rng(105).random((len(fixed), 1 << k_open))
+        ctx.sample_frugal(ps, fixed[:1], u[:1], 10.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        acc, _ = ctx.sample_frugal(ps, fixed, u, 10.0)
+        dt = time.perf_counter() - t
+        res["frugal_sampling"] = {"m_bound": 10.0, "batches": int(len(fixed)),
+                                  "candidates": int(acc.size), "accepted": int(acc.sum()),
+                                  "accept_rate": round(float(acc.mean()), 5),
+                                  "samples_per_s": round(float(acc.sum()) / dt, 1)}
+        ps.close()
         out["diag53_d10"] = res
         print("[bench] diag53_d10 done", file=sys.stderr, flush=True)
     except Exception as e:

@@ -241,6 +241,29 @@ tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                                  const uint8_t *bits, int64_t slice_begin, int64_t slice_end,
                                  double *amps, void *hip_stream, tns_stats *stats);
 
+/* Frugal rejection sampling from correlated batches.  The tensor network's
+ * advantage over a state vector includes simulating measurements
+ * (introduction); with open qubits (tns_plan_opts.open_qubits, k of them)
+ * one contraction yields the 2^k amplitudes of a batch, and each of them is
+ * accepted or rejected on the device by the published frugal rule: candidate
+ * x of batch b is accepted when 2^N |amp(b, x)|^2 / m_bound > uniforms[b][x],
+ * i.e. with probability min(1, 2^N p / m_bound).  When m_bound bounds
+ * 2^N p for every candidate, the accepted bitstrings are distributed as p
+ * (with uniformly random fixed bits); for random circuits p follows the
+ * Porter-Thomas law and about 1 / m_bound of the candidates are accepted.
+ *   fixed_bits  [n_batches][N] 0/1, host; bits of open qubits are ignored.
+ *   uniforms    [n_batches][2^k] in [0, 1), host, supplied by the caller.
+ *   accepted    [n_batches][2^k] 0/1 out, host; candidate x of batch b is
+ *               fixed_bits[b] with its open bits set from x (first open qubit
+ *               most significant, as in tns_amplitudes).
+ *   amps        [n_batches][2^k] complex out (as tns_amplitudes).
+ * Errors: TNS_E_INVALID_ARG for NULL arrays or m_bound <= 0, plus those of
+ * tns_amplitudes.  A plan without open qubits gives one candidate per batch. */
+tns_status tns_sample_frugal(tns_ctx *ctx, const tns_plan *plan, int64_t n_batches,
+                             const uint8_t *fixed_bits, const double *uniforms, double m_bound,
+                             uint8_t *accepted, double *amps, void *hip_stream,
+                             tns_stats *stats);
+
 /* --- serving ---------------------------------------------------------- */
 
 /* Asynchronous request: queued, admitted by memory, and executed by the

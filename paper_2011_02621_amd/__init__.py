@@ -25,7 +25,7 @@ PATH_MODE = {"greedy": 0, "algorithm1": 1}
 
 EXPORTED = ["tns_init", "tns_set_allocator", "tns_finalize", "tns_plan_opts_default",
             "tns_plan_create", "tns_plan_info_get", "tns_plan_destroy", "tns_amplitudes",
-            "tns_amplitudes_sliced",
+            "tns_amplitudes_sliced", "tns_sample_frugal",
             "tns_submit", "tns_poll", "tns_wait", "tns_cancel", "tns_request_free",
             "tns_request_latency", "tns_path_search", "tns_last_error", "tns_version"]
 
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
         "tns_plan_destroy": ([vp], i32),
         "tns_amplitudes": ([vp, vp, i64, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_amplitudes_sliced": ([vp, vp, i64, vp, i64, i64, vp, vp, ctypes.POINTER(_Stats)], i32),
+        "tns_sample_frugal": ([vp, vp, i64, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_submit": ([vp, vp, i64, vp, vp, ctypes.POINTER(vp)], i32),
         "tns_poll": ([vp, ctypes.POINTER(ctypes.c_int)], i32),
         "tns_wait": ([vp], i32),
@@ -360,6 +361,25 @@ class Context:
             out = out.reshape(bits.shape[0], per)
         if stats:
             return out, {f: getattr(st, f) for f, _ in _Stats._fields_}
+        return out
+
+    def sample_frugal(self, plan: Plan, fixed_bits: np.ndarray, uniforms: np.ndarray,
+                      m_bound: float = 10.0, stream: Optional[int] = None, stats: bool = False):
+        """Frugal rejection over correlated batches: (accepted [n][2^k] bool,
+        amplitudes [n][2^k]) for the rows of ``fixed_bits`` and the caller's
+        uniform numbers ``uniforms`` [n][2^k]."""
+        bits = np.ascontiguousarray(fixed_bits, np.uint8).reshape(-1, plan.n_qubits)
+        per = 1 << plan.n_open
+        u = np.ascontiguousarray(uniforms, np.float64).reshape(bits.shape[0], per)
+        acc = np.zeros((bits.shape[0], per), np.uint8)
+        amps = np.zeros((bits.shape[0] * per, 2), np.float64)
+        st = _Stats()
+        _check(load_library().tns_sample_frugal(self._h, plan._h, bits.shape[0], bits.ctypes.data,
+                                                u.ctypes.data, float(m_bound), acc.ctypes.data,
+                                                amps.ctypes.data, stream, ctypes.byref(st)))
+        out = acc.astype(bool), amps.view(np.complex128).reshape(bits.shape[0], per)
+        if stats:
+            return out + ({f: getattr(st, f) for f, _ in _Stats._fields_},)
         return out
 
     def submit(self, plan: Plan, bits: np.ndarray) -> Request:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -383,7 +384,8 @@ tns_status tns_plan_destroy(tns_plan *p) {
 
 static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,
                                   int64_t slice_begin, int64_t slice_end, double *amps,
-                                  void *hip_stream, tns_stats *stats) {
+                                  void *hip_stream, tns_stats *stats,
+                                  const FrugalAccept *frugal = nullptr) {
     return guard([&] {
         auto t0 = clk::now();
         if (!ctx || !plan) fail(TNS_E_INVALID_ARG, "ctx or plan is NULL");
@@ -406,7 +408,7 @@ static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n,
             // share of the budget, like each worker
             const uint64_t budget = ctx->server ? ctx->server->worker_budget : ctx->budget;
             run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, budget, slice_begin,
-                           slice_end);
+                           slice_end, frugal);
         }
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
@@ -442,6 +444,26 @@ tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n, 
         return TNS_E_INVALID_ARG;
     }
     return amplitudes_impl(ctx, plan, n, bits, slice_begin, slice_end, amps, hip_stream, stats);
+}
+
+tns_status tns_sample_frugal(tns_ctx *ctx, const tns_plan *plan, int64_t n_batches,
+                             const uint8_t *fixed_bits, const double *uniforms, double m_bound,
+                             uint8_t *accepted, double *amps, void *hip_stream, tns_stats *stats) {
+    {
+        const tns_status st = guard([&] {
+            if (!plan) fail(TNS_E_INVALID_ARG, "plan is NULL");
+            if (n_batches > 0 && (!uniforms || !accepted || !amps))
+                fail(TNS_E_INVALID_ARG, "uniforms, accepted or amps is NULL");
+            if (!(m_bound > 0.0)) fail(TNS_E_INVALID_ARG, "m_bound must be positive");
+            if (plan->circ.n > 1000) fail(TNS_E_UNSUPPORTED, "2^N overflows");
+        });
+        if (st != TNS_OK) return st;
+    }
+    FrugalAccept fa;
+    fa.uniforms = uniforms;
+    fa.scale = std::ldexp(1.0, plan->circ.n) / m_bound;
+    fa.flags = accepted;
+    return amplitudes_impl(ctx, plan, n_batches, fixed_bits, 0, -1, amps, hip_stream, stats, &fa);
 }
 
 tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8_t *bits,

@@ -292,12 +292,20 @@ struct RunStats {
     double ms_permute = 0, permute_bytes = 0, ms_small = 0;
 };
 
+// Frugal rejection on the device amplitudes: value j is accepted when
+// |amp_j|^2 * scale > uniforms[j]; flags (0/1) go to the host.
+struct FrugalAccept {
+    const double *uniforms = nullptr;   // host, one per amplitude
+    double scale = 0;                   // 2^N / M
+    uint8_t *flags = nullptr;           // host, one per amplitude
+};
+
 // Amplitudes of bitstrings [0, n) into host amps (complex128 pairs), using at
 // most `budget` bytes of workspace beyond the plan's resident tensors.
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
-                    int64_t slice_end = -1);
+                    int64_t slice_end = -1, const FrugalAccept *frugal = nullptr);
 int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
 
 // ----------------------------------------------------------------------------
@@ -341,6 +349,8 @@ void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64
                     void *stream);
 void final_dot(const void *A, const void *Bt, double *partial, int64_t units, int64_t K,
                int64_t sA, int64_t sB, int c64, void *stream);
+void frugal_accept(const double *amps, const double *uniforms, double scale, uint8_t *flags,
+                   int64_t n, void *stream);
 void slice_sum(const double *partial, double *amps, int64_t nb, int64_t n_slices, int64_t per,
                void *stream);
 void finalize(const void *T, double *partial, int64_t units, int64_t t_us, int64_t per,

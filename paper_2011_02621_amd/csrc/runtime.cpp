@@ -250,7 +250,7 @@ struct Timer {
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin,
-                    int64_t slice_end) {
+                    int64_t slice_end, const FrugalAccept *frugal) {
     const Circuit &c = p.circ;
     if (slice_end < 0) slice_end = p.n_slices;
     const int64_t n_sl = slice_end - slice_begin;   // slices computed per bitstring
@@ -408,6 +408,16 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         }
         st.units += units;
         st.flops += p.flops_per_amp * nb * ((double)n_sl / (double)p.n_slices);
+    }
+    if (frugal) {
+        const int64_t na = n * opu;
+        double *u_dev = (double *)ws.get(ctx, S_BITS, (size_t)na * 9, stream);
+        uint8_t *f_dev = (uint8_t *)(u_dev + na);
+        hip_check(hipMemcpyAsync(u_dev, frugal->uniforms, (size_t)na * 8, hipMemcpyHostToDevice,
+                                 (hipStream_t)stream), "uniforms upload");
+        launch::frugal_accept(amps_dev, u_dev, frugal->scale, f_dev, na, stream);
+        hip_check(hipMemcpyAsync(frugal->flags, f_dev, (size_t)na, hipMemcpyDeviceToHost,
+                                 (hipStream_t)stream), "flags download");
     }
     hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * opu * 16, hipMemcpyDeviceToHost,
                              (hipStream_t)stream), "amplitude download");

@@ -51,6 +51,18 @@ def _two_qubit_circuit(n, edges, ops):
     return Circuit(n, edges, gates, 1)
 
 
+def test_sample_frugal_argument_errors(ctx):
+    c, bits = config("grid3x4_d8")
+    p = ctx.plan(c, open_qubits=[0, 1])
+    u = np.zeros((2, 4))
+    with pytest.raises(T.TnsError) as e:
+        ctx.sample_frugal(p, bits[:2], u, m_bound=0.0)
+    assert e.value.name == "TNS_E_INVALID_ARG"
+    with pytest.raises(T.TnsError) as e:
+        ctx.sample_frugal(p, bits[:2], u, m_bound=10.0)
+    assert e.value.name == "TNS_E_NO_DEVICE"
+
+
 def test_bad_circuits(ctx):
     good = _two_qubit_circuit(2, [(0, 1)], [(0, 1, 0, fsim(np.pi / 2, np.pi / 6))])
     ctx.plan(good)

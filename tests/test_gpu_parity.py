@@ -12,7 +12,7 @@ import pytest
 
 import paper_2011_02621_amd as T
 from circuits import config, grid, diagonal53, random_circuit, mirror_circuit, bitstrings
-from oracle import sv, stabilizer
+from oracle import sv, stabilizer, sampling
 from oracle.metrics import compare
 
 pytestmark = pytest.mark.gpu
@@ -261,6 +261,30 @@ def test_clifford_104_against_tableau(ctx, prec):
     got = ctx.amplitudes(p, bits)
     tol = TOL[prec]
     assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 2 * tol * max(p_ref.max(), 2.0 ** -104)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_frugal_sampling(ctx, prec):
+    # correlated batches of 2^3 candidates; decisions against the oracle's
+    # FP64 probabilities with the same uniform numbers (a decision may differ
+    # only where 2^N p / M lies within the amplitude error of u)
+    c, _ = config("grid3x4_d8")
+    oq = [11, 0, 5]
+    fixed = bitstrings(12, 16, 41)
+    u = np.random.default_rng(42).random((16, 8))
+    m = 2.0
+    say("frugal sampling", prec)
+    p = ctx.plan(c, precision=prec, open_qubits=oq)
+    acc, amps = ctx.sample_frugal(p, fixed, u, m)
+    cand = sampling.batch_bitstrings(fixed, oq)
+    ref = sv.amplitudes(c, cand.reshape(-1, 12)).reshape(16, 8)
+    check(ref.reshape(-1), amps.reshape(-1), c.n, prec)
+    acc_ref = sampling.frugal_accept(np.abs(ref) ** 2, u, c.n, m)
+    margin = np.abs(np.abs(ref) ** 2 * 2.0 ** c.n / m - u)
+    differ = acc != acc_ref
+    thr = 1e-6 if prec == "c64" else 1e-12
+    assert not np.any(differ & (margin > thr))
+    assert 0 < acc.sum() < acc.size
 
 
 def test_stream_argument(ctx, small):
