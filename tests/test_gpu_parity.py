@@ -287,6 +287,35 @@ def test_frugal_sampling(ctx, prec):
     assert 0 < acc.sum() < acc.size
 
 
+def test_empty_single_and_duplicate_batches(ctx, small):
+    c, bits, ref = small
+    p = ctx.plan(c, precision="c128")
+    say("empty / single / duplicate batches")
+    assert ctx.amplitudes(p, bits[:0]).shape == (0,)
+    got1 = ctx.amplitudes(p, bits[3:4])
+    assert abs(got1[0] - ref[3]) <= 1e-10 * np.linalg.norm(ref) / np.sqrt(len(ref))
+    dup = np.repeat(bits[5:6], 9, axis=0)
+    got = ctx.amplitudes(p, dup)
+    assert np.all(got == got[0]) and abs(got[0] - ref[5]) < 1e-10 * np.abs(ref).max()
+
+
+def test_small_budget_ragged_batches():
+    # a 48 MiB budget forces small bitstring batches and few units per
+    # launch, with ragged tails in both; 4100 bitstrings also exceed the
+    # per-batch cap of 4096
+    c, _ = config("grid3x4_d8")
+    bits = bitstrings(12, 4100, 77)
+    ref = sv.amplitudes(c, bits)
+    say("small budget, 4100 bitstrings")
+    small_ctx = T.Context(0, 48 << 20)
+    try:
+        for prec in ("c128", "c64"):
+            got = small_ctx.amplitudes(small_ctx.plan(c, precision=prec), bits)
+            check(ref, got, c.n, prec)
+    finally:
+        small_ctx.close()
+
+
 def test_stream_argument(ctx, small):
     import torch
     c, bits, ref = small
