@@ -1159,6 +1159,25 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
             needs_cuts[k] = !sl.cuts.empty();
         }
         double best = *std::min_element(total.begin(), total.end());
+        // the greedy score can rank splits differently from the path search
+        // that builds the final path: score the cut-free splits near the best
+        // (within 1.5x, at most six) with the requested mode as well
+        if (opts.path_mode != TNS_PATH_GREEDY) {
+            std::vector<int> near;
+            for (int k = 0; k <= depth; ++k)
+                if (!needs_cuts[k] && total[k] <= 1.5 * best) near.push_back(k);
+            std::sort(near.begin(), near.end(), [&](int a2, int b2) { return total[a2] < total[b2]; });
+            if (near.size() > 6) near.resize(6);
+            for (int k : near) {
+                evolve_both(p, k);
+                std::vector<double> d(p.bond_overlap.begin(), p.bond_overlap.end());
+                PathResult r = path_search(c.n, c.g.edges, d, opts.path_mode, opts.max_rank,
+                                           opts.path_assumptions != 0, opts.max_search_states);
+                Sliced sl = cuts_for_order(p, r.order, {}, limit);
+                if (sl.peak <= limit) total[k] = std::min(total[k], sl.total);
+            }
+            best = *std::min_element(total.begin(), total.end());
+        }
         std::vector<int> byscore(depth + 1);
         std::iota(byscore.begin(), byscore.end(), 0);
         std::sort(byscore.begin(), byscore.end(), [&](int a2, int b2) { return score0[a2] < score0[b2]; });

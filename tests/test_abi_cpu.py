@@ -145,15 +145,18 @@ def test_permutes_fused_into_gemm_stores(ctx):
     c, _ = config("grid5x5_d10")
     for prec in ("c64", "c128"):
         i = ctx.plan(c, precision=prec).info()
+        # the step arrays start at the first contraction (entry t is step t+1
+        # after the starting tensor); a fused permute needs a GEMM before it
         sp, k = np.asarray(i.step_permute), np.asarray(i.step_kernel)
         assert (sp == 2).sum() > 0
         for t in np.nonzero(sp == 2)[0]:
-            assert t >= 2 and k[t - 1] == 0
+            assert t >= 1 and k[t - 1] == 0
         for t in np.nonzero(sp == 1)[0]:
-            assert t < 2 or k[t - 1] != 0
-        # permute launches only: bytes of the fused ones are not counted
+            assert t == 0 or k[t - 1] != 0
+        # permute launches only (the permuted tensor holds M * K elements):
+        # the fused ones are not counted
         elem = 16 if prec == "c128" else 8
-        launched = sum(2.0 * elem * i.step_m[t - 1] * i.step_n[t - 1] for t in np.nonzero(sp == 1)[0])
+        launched = sum(2.0 * elem * i.step_m[t] * i.step_k[t] for t in np.nonzero(sp == 1)[0])
         assert i.permute_bytes_per_amp == pytest.approx(launched * i.n_slices)
 
 
