@@ -347,8 +347,12 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     using ET = typename std::conditional<MODE == 1, float, __bf16>::type;
     constexpr int APART = BM * LD, BPART = BN * LD;
     static_assert(NSTAGE == 1 || NSTAGE == 2, "one or two LDS stages");
-    __shared__ ET As[NSTAGE][NSPLIT * APART];
-    __shared__ ET Bs[NSTAGE][NSPLIT * BPART];
+    // one LDS array: the A stages, then the B stages (the fused store stages
+    // its output through all of it after the k-loop)
+    constexpr int SMEM = NSTAGE * NSPLIT * (APART + BPART);
+    __shared__ ET smem[SMEM];
+    auto As = [&](int st) { return smem + st * NSPLIT * APART; };
+    auto Bs = [&](int st) { return smem + NSTAGE * NSPLIT * APART + st * NSPLIT * BPART; };
     // a k-tile row is BK/4 float4; 256 threads cover RPP rows per pass;
     // float4 loads per thread, a B tile narrower than one pass leaving the
     // threads with lrow >= BN idle
@@ -392,14 +396,14 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     auto stash = [&](int stage) {
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
-            ET *dst = &As[stage][(lrow + RPP * i) * LD + lcol];
+            ET *dst = As(stage) + (lrow + RPP * i) * LD + lcol;
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = ra[i];
             else split_store<NSPLIT>(dst, APART, ra[i]);
         }
 #pragma unroll
         for (int i = 0; i < BV; ++i) {
             if (BPART_PASS && lrow + RPP * i >= BN) continue;
-            ET *dst = &Bs[stage][(lrow + RPP * i) * LD + lcol];
+            ET *dst = Bs(stage) + (lrow + RPP * i) * LD + lcol;
             if constexpr (MODE == 1) *reinterpret_cast<v4f *>(dst) = rb[i];
             else split_store<NSPLIT>(dst, BPART, rb[i]);
         }
@@ -411,8 +415,8 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     for (int k0 = 0; k0 < Kr; k0 += BK) {
         const bool more = k0 + BK < Kr;
         if (more) fetch(k0 + BK);
-        const ET *Ac = As[stage];
-        const ET *Bc = Bs[stage];
+        const ET *Ac = As(stage);
+        const ET *Bc = Bs(stage);
         if constexpr (MODE == 1) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 8) {
@@ -491,16 +495,16 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
                     if (row < M && col < Nr) C[row * Nr + col] = acc[i][j][r];
                 }
     } else {
-        // Fused store, staged per wave through LDS (the A stages are free
-        // after the k-loop's last barrier): each 32-column slice of the
+        // Fused store, staged per wave through LDS (the operand stages are
+        // free after the k-loop's last barrier): each 32-column slice of the
         // wave's tile is written in the accumulator layout and read back one
         // complex value per lane in the order in which the target is
         // contiguous (rows when sc.mfast, else columns).
         constexpr int WR = BI * 32;   // rows of the wave's tile
         constexpr int CW = 16;        // complex columns of a slice
         constexpr int SLD = 34;       // staging row: 32 floats + 2 (keeps float2 alignment)
-        static_assert(4 * WR * SLD * sizeof(float) <= sizeof(As), "staging fits in the A stages");
-        float *stg = reinterpret_cast<float *>(&As[0][0]) + wave * WR * SLD;
+        static_assert(4 * WR * SLD * sizeof(float) <= SMEM * sizeof(ET), "staging fits in the stages");
+        float *stg = reinterpret_cast<float *>(smem) + wave * WR * SLD;
         fused_store_wave<float2, WR, CW, SLD, BJ>(
             C, stg, sc, row0, m0 + wm * WR, M, n0 + wn * BJ * 32, Nr, lane, [&](int j) {
 #pragma unroll
@@ -912,13 +916,27 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
 }
 
 // NSTAGE: two LDS stages on the 128 x 128 tile (k-step 32: 73.7 KB FP32,
-// 81.9 KB 3-product BF16; the 6-product form takes k-step 16, 61.4 KB), so
-// two blocks fit on a CU; one stage on the narrow tiles.
+// 81.9 KB 3-product BF16; k-step 16 for short k-loops and for the 6-product
+// form, 40.9 / 49.2 / 61.4 KB), so two blocks fit on a CU; one stage on the
+// narrow tiles.
 template <int BI, int BJ, int WGM, int WGN, bool SCAT>
 static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, const float *B, float *C,
                        int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n,
                        const ScatterStore &sc, int64_t row0) {
     constexpr int S = WGN == 2 ? 2 : 1;
+    // measured: on the 128 x 128 tile a k-step of 16 pays for short k-loops
+    // (2K < 1024), a k-step of 32 for long ones
+    if constexpr (S == 2) {
+        if (Kr < 1024 && (mode == 1 || mode == 2)) {
+            if (mode == 1)
+                hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                                   Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+            else
+                hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                                   Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+            return;
+        }
+    }
     if (mode == 1)
         hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
                            sA, sB, sC, tiles_n, sc, row0);
