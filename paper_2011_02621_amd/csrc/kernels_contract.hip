@@ -321,10 +321,10 @@ __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, cons
 // 4 waves in a WGM x WGN layout; each wave owns BI x BJ blocks of 32 x 32, so
 // the tile is (WGM*BI*32) x (WGN*BJ*32), k-step BK reals.  The next k-tile is
 // fetched into registers while the current one is multiplied out of LDS.
-// NSTAGE = 2 keeps two LDS k-tiles, so the next one is stored while the
-// current one is read and a k-step needs one barrier; it doubles the LDS of a
-// block, which pays where two blocks still fit on a CU (the 128 x 128 tile)
-// and costs occupancy on the narrow tiles, which keep NSTAGE = 1.
+// NSTAGE = 2 keeps two LDS k-tiles, so the next one is stored half-way
+// through the current one and a k-step needs one barrier; it doubles the LDS
+// of a block, which pays where two blocks still fit on a CU (the 128 x 128
+// tile) and costs occupancy on the narrow tiles, which keep NSTAGE = 1.
 // MODE 1: FP32 operands, v_mfma_f32_32x32x2f32; the two k-slots of an MFMA
 // (lanes 0-31 / 32-63) take k = 4*slot + t for the four MFMAs t of an
 // 8-wide k group, so each lane reads its values with one 16-byte LDS load.
@@ -378,7 +378,31 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     const int lrow = tid / TPR, lcol = (tid % TPR) * 4;
     v4f ra[AV], rb[BV];
+    // Row pointers clamped into the operands: a row past M (or Nr) loads the
+    // last valid row, whose products are never stored, so a full k-tile is
+    // fetched without guards or branches; only a partial last k-tile checks k
+    // (the two-stage tiles).
+    const float *ap[AV], *bp[BV];
+#pragma unroll
+    for (int i = 0; i < AV; ++i) ap[i] = A + std::min<int64_t>(m0 + lrow + RPP * i, M - 1) * Kr + lcol;
+#pragma unroll
+    for (int i = 0; i < BV; ++i) bp[i] = Bt + (int64_t)std::min(n0 + lrow + RPP * i, Nr - 1) * Kr + lcol;
     auto fetch = [&](int k0) {
+        if (k0 + BK <= Kr) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) ra[i] = *reinterpret_cast<const v4f *>(ap[i] + k0);
+#pragma unroll
+            for (int i = 0; i < BV; ++i) rb[i] = *reinterpret_cast<const v4f *>(bp[i] + k0);
+        } else {
+            const bool in = k0 + lcol < Kr;
+#pragma unroll
+            for (int i = 0; i < AV; ++i) ra[i] = in ? *reinterpret_cast<const v4f *>(ap[i] + k0) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < BV; ++i) rb[i] = in ? *reinterpret_cast<const v4f *>(bp[i] + k0) : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    // the single-stage narrow tiles keep per-row guards (measured faster there)
+    auto fetch_guarded = [&](int k0) {
         const int gk = k0 + lcol;
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
@@ -390,7 +414,8 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
         for (int i = 0; i < BV; ++i) {
             const int gn = n0 + lrow + RPP * i;
             rb[i] = v4f{0.f, 0.f, 0.f, 0.f};
-            if (gn < Nr && gk < Kr && (!BPART_PASS || lrow + RPP * i < BN)) rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
+            if (gn < Nr && gk < Kr && (!BPART_PASS || lrow + RPP * i < BN))
+                rb[i] = *reinterpret_cast<const v4f *>(Bt + (int64_t)gn * Kr + gk);
         }
     };
     auto stash = [&](int stage) {
@@ -408,72 +433,92 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
             else split_store<NSPLIT>(dst, BPART, rb[i]);
         }
     };
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    int stage = 0;
-    for (int k0 = 0; k0 < Kr; k0 += BK) {
-        const bool more = k0 + BK < Kr;
-        if (more) fetch(k0 + BK);
-        const ET *Ac = As(stage);
-        const ET *Bc = Bs(stage);
+    // Fragments of one k-group (8 reals for MODE 1, 16 for MODE 2 / 3); the
+    // two-stage tiles keep two register sets, so the next group's LDS reads
+    // are in flight during the current group's MFMAs.
+    constexpr int KG = MODE == 1 ? 8 : 16, NG = BK / KG;
+    using FT = typename std::conditional<MODE == 1, v4f, bf16x8>::type;
+    FT fa[2][BI][NSPLIT], fb[2][BJ][NSPLIT];
+    const int arow = (wm * BI * 32 + (lane & 31)) * LD + (KG / 2) * (lane >> 5);
+    const int brow = (wn * BJ * 32 + (lane & 31)) * LD + (KG / 2) * (lane >> 5);
+    auto frags = [&](int buf, const ET *Ac, const ET *Bc, int kk) {
+#pragma unroll
+        for (int p = 0; p < NSPLIT; ++p) {
+#pragma unroll
+            for (int i = 0; i < BI; ++i)
+                fa[buf][i][p] = *reinterpret_cast<const FT *>(&Ac[p * APART + arow + i * 32 * LD + kk]);
+#pragma unroll
+            for (int j = 0; j < BJ; ++j)
+                fb[buf][j][p] = *reinterpret_cast<const FT *>(&Bc[p * BPART + brow + j * 32 * LD + kk]);
+        }
+    };
+    auto mfma_group = [&](int buf) {
         if constexpr (MODE == 1) {
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 8) {
-                const int kofs = kk + 4 * (lane >> 5);
-                v4f a[BI], b[BJ];
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int i = 0; i < BI; ++i)
-                    a[i] = *reinterpret_cast<const v4f *>(&Ac[(wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
-#pragma unroll
-                for (int j = 0; j < BJ; ++j)
-                    b[j] = *reinterpret_cast<const v4f *>(&Bc[(wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int i = 0; i < BI; ++i)
-#pragma unroll
-                        for (int j = 0; j < BJ; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                const int kofs = kk + 8 * (lane >> 5);
-                bf16x8 a[BI][NSPLIT], b[BJ][NSPLIT];
-#pragma unroll
-                for (int p = 0; p < NSPLIT; ++p) {
-#pragma unroll
-                    for (int i = 0; i < BI; ++i)
-                        a[i][p] = *reinterpret_cast<const bf16x8 *>(
-                            &Ac[p * APART + (wm * BI * 32 + i * 32 + (lane & 31)) * LD + kofs]);
 #pragma unroll
                     for (int j = 0; j < BJ; ++j)
-                        b[j][p] = *reinterpret_cast<const bf16x8 *>(
-                            &Bc[p * BPART + (wn * BJ * 32 + j * 32 + (lane & 31)) * LD + kofs]);
-                }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[buf][i][0][t], fb[buf][j][0][t], acc[i][j], 0, 0, 0);
+        } else {
 #pragma unroll
-                for (int i = 0; i < BI; ++i)
+            for (int i = 0; i < BI; ++i)
 #pragma unroll
-                    for (int j = 0; j < BJ; ++j) {
-                        // smallest terms first
-                        if constexpr (NSPLIT == 3) {
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], acc[i][j], 0, 0, 0);
-                        }
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < BJ; ++j) {
+                    // smallest terms first
+                    if constexpr (NSPLIT == 3) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][2], fb[buf][j][0], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][1], fb[buf][j][1], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][0], fb[buf][j][2], acc[i][j], 0, 0, 0);
                     }
-            }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][1], fb[buf][j][0], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][0], fb[buf][j][1], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[buf][i][0], fb[buf][j][0], acc[i][j], 0, 0, 0);
+                }
         }
-        if constexpr (NSTAGE == 2) {
-            // the other stage was last read before the previous barrier
-            if (more) stash(stage ^ 1);
+    };
+    if constexpr (NSTAGE == 2) {
+        // Two LDS stages and two register k-tiles in flight: tile t+1 is
+        // already in registers when tile t starts; half-way through tile t it
+        // goes to the other stage (last read in tile t-1, before the previous
+        // barrier) and the fetch of tile t+2 is issued, so global latency
+        // spans a whole tile and the barrier at the end waits on no store.
+        constexpr int MID = NG > 1 ? NG / 2 - 1 : 0;
+        fetch(0);
+        stash(0);
+        if (BK < Kr) fetch(BK);
+        __syncthreads();
+        int stage = 0;
+        for (int k0 = 0; k0 < Kr; k0 += BK) {
+            const bool more = k0 + BK < Kr, more2 = k0 + 2 * BK < Kr;
+            const ET *Ac = As(stage), *Bc = Bs(stage);
+            frags(0, Ac, Bc, 0);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (g + 1 < NG) frags((g + 1) & 1, Ac, Bc, (g + 1) * KG);
+                mfma_group(g & 1);
+                if (g == MID && more) {
+                    stash(stage ^ 1);
+                    if (more2) fetch(k0 + 2 * BK);
+                }
+            }
             __syncthreads();
             stage ^= 1;
-        } else {
+        }
+    } else {
+        fetch_guarded(0);
+        stash(0);
+        __syncthreads();
+        for (int k0 = 0; k0 < Kr; k0 += BK) {
+            const bool more = k0 + BK < Kr;
+            if (more) fetch_guarded(k0 + BK);
+            const ET *Ac = As(0), *Bc = Bs(0);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                frags(0, Ac, Bc, g * KG);
+                mfma_group(0);
+            }
             __syncthreads();
             if (more) {
                 stash(0);
@@ -521,7 +566,8 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 // 16.  The four k-slots (lanes 16*slot .. 16*slot+15) map to k = 4*slot + t
 // for the four MFMAs t of a 16-wide k group.  The next k-tile is fetched into
 // registers during the current one's MFMAs; NSTAGE = 2 keeps two LDS stages
-// (one barrier per k-step) as in the FP32 kernel.
+// (one barrier per k-step, the next tile stored half-way through the current
+// one) as in the FP32 kernel.
 constexpr int F64_BK = 16, F64_LD = F64_BK + 2;
 
 template <int BI, int BJ, int NSTAGE, bool SCAT>
@@ -554,22 +600,24 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
     const int lrow = tid >> 2, lcol = (tid & 3) * 4;
     v2d ra[AP][2], rb[BP][2];
+    // row pointers clamped into the operands, as in the FP32 kernel: a full
+    // k-tile is fetched without guards, a partial last one checks k
+    const double *ap[AP], *bp[BP];
+#pragma unroll
+    for (int p = 0; p < AP; ++p) ap[p] = A + std::min<int64_t>(m0 + lrow + 64 * p, M - 1) * Kr + lcol;
+#pragma unroll
+    for (int p = 0; p < BP; ++p) bp[p] = Bt + (int64_t)std::min(n0 + lrow + 64 * p, Nr - 1) * Kr + lcol;
     auto fetch = [&](int k0) {
+        const bool full = k0 + F64_BK <= Kr;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int gk = k0 + lcol + 2 * h;
+            const bool in = full || k0 + lcol + 2 * h < Kr;
 #pragma unroll
-            for (int p = 0; p < AP; ++p) {
-                const int64_t gm = m0 + lrow + 64 * p;
-                ra[p][h] = v2d{0.0, 0.0};
-                if (gm < M && gk < Kr) ra[p][h] = *reinterpret_cast<const v2d *>(A + gm * Kr + gk);
-            }
+            for (int p = 0; p < AP; ++p)
+                ra[p][h] = in ? *reinterpret_cast<const v2d *>(ap[p] + k0 + 2 * h) : v2d{0.0, 0.0};
 #pragma unroll
-            for (int p = 0; p < BP; ++p) {
-                const int gn = n0 + lrow + 64 * p;
-                rb[p][h] = v2d{0.0, 0.0};
-                if (gn < Nr && gk < Kr) rb[p][h] = *reinterpret_cast<const v2d *>(Bt + (int64_t)gn * Kr + gk);
-            }
+            for (int p = 0; p < BP; ++p)
+                rb[p][h] = in ? *reinterpret_cast<const v2d *>(bp[p] + k0 + 2 * h) : v2d{0.0, 0.0};
         }
     };
     auto stash = [&](int stage) {
@@ -583,16 +631,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
                 *reinterpret_cast<v2d *>(&Bs[stage][(lrow + 64 * p) * F64_LD + lcol + 2 * h]) = rb[p][h];
         }
     };
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    int stage = 0;
-    for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
-        const bool more = k0 + F64_BK < Kr;
-        if (more) fetch(k0 + F64_BK);
-        const double *Ac = As[stage], *Bc = Bs[stage];
-        const int kofs = 4 * (lane >> 4);
-        v4d a[BI], b[BJ];
+    const int kofs = 4 * (lane >> 4);
+    auto mfmas = [&](const v4d *a, const v4d *b, int t0, int t1) {
+#pragma unroll
+        for (int t = t0; t < t1; ++t)
+#pragma unroll
+            for (int i = 0; i < BI; ++i)
+#pragma unroll
+                for (int j = 0; j < BJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+    };
+    auto frags = [&](v4d *a, v4d *b, const double *Ac, const double *Bc) {
 #pragma unroll
         for (int i = 0; i < BI; ++i) {
             const double *q = &Ac[(wm * BI * 16 + i * 16 + (lane & 15)) * F64_LD + kofs];
@@ -603,18 +652,38 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
             const double *q = &Bc[(wn * BJ * 16 + j * 16 + (lane & 15)) * F64_LD + kofs];
             b[j] = v4d{q[0], q[1], q[2], q[3]};
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int i = 0; i < BI; ++i)
-#pragma unroll
-                for (int j = 0; j < BJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
-        if constexpr (NSTAGE == 2) {
-            if (more) stash(stage ^ 1);
+    };
+    if constexpr (NSTAGE == 2) {
+        // tile t+1 waits in registers; half-way through tile t it goes to the
+        // other stage and the fetch of tile t+2 is issued (as in the FP32 kernel)
+        fetch(0);
+        stash(0);
+        if (F64_BK < Kr) fetch(F64_BK);
+        __syncthreads();
+        int stage = 0;
+        for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
+            const bool more = k0 + F64_BK < Kr, more2 = k0 + 2 * F64_BK < Kr;
+            v4d a[BI], b[BJ];
+            frags(a, b, As[stage], Bs[stage]);
+            mfmas(a, b, 0, 2);
+            if (more) {
+                stash(stage ^ 1);
+                if (more2) fetch(k0 + 2 * F64_BK);
+            }
+            mfmas(a, b, 2, 4);
             __syncthreads();
             stage ^= 1;
-        } else {
+        }
+    } else {
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
+            const bool more = k0 + F64_BK < Kr;
+            if (more) fetch(k0 + F64_BK);
+            v4d a[BI], b[BJ];
+            frags(a, b, As[0], Bs[0]);
+            mfmas(a, b, 0, 4);
             __syncthreads();
             if (more) {
                 stash(0);
