@@ -993,28 +993,41 @@ static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, cons
                        int64_t M, int Kr, int Nr, int64_t sA, int64_t sB, int64_t sC, int tiles_n,
                        const ScatterStore &sc, int64_t row0) {
     constexpr int S = WGN == 2 ? 2 : 1;
-    // measured: on the 128 x 128 tile a k-step of 16 pays for short k-loops
-    // (2K < 1024), a k-step of 32 for long ones
-    if constexpr (S == 2) {
-        if (Kr < 1024 && (mode == 1 || mode == 2)) {
-            if (mode == 1)
-                hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
-                                   Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
-            else
-                hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
-                                   Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
-            return;
+    if constexpr (BJ == 4) {
+        // 128 x 256 (FP32 and split-BF16 x3): k-step 16, since two stages at
+        // k-step 32 would leave one block per CU
+        if (mode == 1)
+            hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, 2, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                               Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+        else if (mode == 2)
+            hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, 2, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                               Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+        else
+            fail(TNS_E_UNSUPPORTED, "internal: no 128 x 256 tile for split-BF16 x6");
+    } else {
+        // measured: on the 128 x 128 tile a k-step of 16 pays for short k-loops
+        // (2K < 1024), a k-step of 32 for long ones
+        if constexpr (S == 2) {
+            if (Kr < 1024 && (mode == 1 || mode == 2)) {
+                if (mode == 1)
+                    hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                                       Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+                else
+                    hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                                       Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+                return;
+            }
         }
+        if (mode == 1)
+            hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
+                               sA, sB, sC, tiles_n, sc, row0);
+        else if (mode == 2)
+            hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
+                               sA, sB, sC, tiles_n, sc, row0);
+        else
+            hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, S, (S == 2 ? 16 : 32), SCAT>), grid, dim3(256), 0, st, A,
+                               B, C, M, Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
     }
-    if (mode == 1)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
-                           sA, sB, sC, tiles_n, sc, row0);
-    else if (mode == 2)
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 32, SCAT>), grid, dim3(256), 0, st, A, B, C, M, Kr, Nr,
-                           sA, sB, sC, tiles_n, sc, row0);
-    else
-        hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 3, S, (S == 2 ? 16 : 32), SCAT>), grid, dim3(256), 0, st, A,
-                           B, C, M, Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
 }
 
 template <int BI, int BJ, int WGM, int WGN>
@@ -1047,12 +1060,16 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
     // tile shape: complex64 256 x 32 for N <= 16 complex, 256 x 64 for N <= 32,
-    // else 128 x 128; complex128 128 x 128 for N >= 128 complex and M >= 4096,
-    // else 64 x 64 (measured: the large tile loses on narrow and short shapes)
+    // else 128 x 128, or 128 x 256 for N >= 256 complex with split-BF16 x3
+    // (+5-8 %) or FP32 with 2K >= 1024 (+0.5-1 %; split-BF16 x6 loses there,
+    // its fragments leave one block per CU); complex128 128 x 128 for N >= 128
+    // complex and M >= 4096, else 64 x 64 (measured: the large tiles lose on
+    // narrow and short shapes)
     const bool f64_big = Nr >= 256 && M >= 4096;
-    const int shape = !c64 ? (f64_big ? 4 : 0) : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : 3));
-    const int BM = shape == 0 ? 64 : (shape == 3 || shape == 4 ? 128 : 256);
-    const int BN = shape == 0 ? 64 : (shape == 1 ? 32 : (shape == 2 ? 64 : 128));
+    const bool wide = Nr >= 512 && (mode == 2 || (mode == 1 && Kr >= 1024));
+    const int shape = !c64 ? (f64_big ? 4 : 0) : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : (wide ? 5 : 3)));
+    const int BM = shape == 0 ? 64 : (shape == 3 || shape == 4 || shape == 5 ? 128 : 256);
+    const int BN = shape == 0 ? 64 : (shape == 1 ? 32 : (shape == 2 ? 64 : (shape == 5 ? 256 : 128)));
     const int tiles_n = (Nr + BN - 1) / BN;
     // rows per launch so that the grid stays below 2^31 blocks
     const int64_t max_tiles_m = ((int64_t)1 << 30) / tiles_n;
@@ -1072,7 +1089,8 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
                 float *c = (float *)C + 2 * (u0 * sC + crow * N);
                 if (shape == 1) launch_c64<2, 1, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
                 else if (shape == 2) launch_c64<2, 2, 4, 1>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
-                else launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
+                else if (shape == 3) launch_c64<2, 2, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
+                else launch_c64<2, 4, 2, 2>(mode, grid, st, a, b, c, mr, Kr, Nr, 2 * sA, 4 * sB, 2 * sC, tiles_n, sc, r0);
             } else {
                 const double *a = (const double *)A + 2 * (u0 * sA + r0 * K);
                 const double *b = (const double *)Bt + 4 * u0 * sB;
