@@ -142,7 +142,8 @@ typedef struct {
     const int64_t *step_n;          /* [n_steps] new-leg product */
     const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM, 1 small, 2 final dot */
     const int32_t *step_permute;    /* [n_steps] 0 no permute, 1 permute launch, 2 permute done
-                                       by the previous GEMM's store (fused) */
+                                       by the previous step's store (fused; a GEMM, or a
+                                       small-bond step with at least 64 rows) */
     const int32_t *bond_ket;        /* [n_edges] ket bond dimensions */
     const int32_t *bond_bra;        /* [n_edges] bra bond dimensions */
     const int32_t *bond_overlap;    /* [n_edges] overlap bond dimensions */

@@ -123,6 +123,19 @@ struct ScatterStore {
     int mfast = 0;   // 1: consecutive rows are consecutive in the target, 0: columns
 };
 
+// LDS budget of the row-tiled small-step kernel: rows of A (padded by one
+// complex) in kSmallRowsA bytes, at least 8 of them, and B^T (N x K, padded
+// likewise) in kSmallRowsB.
+constexpr int64_t kSmallRowsA = 32768, kSmallRowsB = 16384;
+inline int64_t small_rows_block(int64_t K, int64_t csize) {
+    const int64_t rb = kSmallRowsA / ((K + 1) * csize);
+    return rb < 256 ? rb : 256;
+}
+// csize: bytes per complex element (8 for complex64, 16 for complex128)
+inline bool small_rows_fits(int64_t M, int64_t K, int64_t N, int64_t csize) {
+    return M >= 64 && small_rows_block(K, csize) >= 8 && N * (K + 1) * csize <= kSmallRowsB;
+}
+
 struct Step {
     int site = -1;                       // tensor absorbed (i_{m+1}); for step 0 the start
     std::vector<int> t_legs;             // boundary legs before the step (storage order)
@@ -344,9 +357,13 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
           const ScatterStore *sc = nullptr);
+// Steps with a small bond (K or N < 16, or M < 16).  With many rows and a
+// small B (small_rows_fits) a block stages whole rows of A and all of B in
+// LDS and may store through fused-store tables (sc); otherwise one thread per
+// output element, plain stores only.
 void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
                     int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
-                    void *stream);
+                    void *stream, const ScatterStore *sc = nullptr);
 void final_dot(const void *A, const void *Bt, double *partial, int64_t units, int64_t K,
                int64_t sA, int64_t sB, int c64, void *stream);
 void frugal_accept(const double *amps, const double *uniforms, double scale, uint8_t *flags,

@@ -732,7 +732,68 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
-// small steps: one thread per output element, C[u][m][n] = sum_k A[u][m][k] B[u][n][k]
+// small steps, C[u][m][n] = sum_k A[u][m][k] B[u][n][k] with a small K or N.
+// k_small_rows: a block copies RB consecutive rows of A (one unit, contiguous)
+// and all of B into LDS with coalesced complex loads (rows padded by one
+// complex against bank conflicts), then its threads produce the RB x N
+// outputs from LDS.  Outputs are stored row-major (consecutive threads,
+// consecutive addresses) or through the fused-store tables in the order in
+// which the target is contiguous.  HBM traffic: A and C once.
+template <typename R, bool SCAT>
+__global__ __launch_bounds__(256) void k_small_rows(const R *__restrict__ A, const R *__restrict__ Bt,
+                                                    R *__restrict__ C, int64_t M, int K, int N, int RB,
+                                                    int64_t sA, int64_t sB, int64_t sC, ScatterStore sc) {
+    using C2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    __shared__ C2 As[kSmallRowsA / sizeof(C2)];
+    __shared__ C2 Bs[kSmallRowsB / sizeof(C2)];
+    const int64_t u = blockIdx.y;
+    const int64_t m0 = (int64_t)blockIdx.x * RB;
+    const int rows = (int)(M - m0 < RB ? M - m0 : RB);
+    const int tid = threadIdx.x, ld = K + 1;
+    const C2 *a = reinterpret_cast<const C2 *>(A) + u * sA + m0 * K;
+    const C2 *b = reinterpret_cast<const C2 *>(Bt) + u * sB;
+    const int na = rows * K, nb = N * K;
+    for (int i = tid; i < na; i += 256) {
+        const int r = i / K;
+        As[r * ld + (i - r * K)] = a[i];
+    }
+    for (int i = tid; i < nb; i += 256) {
+        const int n = i / K;
+        Bs[n * ld + (i - n * K)] = b[i];
+    }
+    __syncthreads();
+    C2 *c = reinterpret_cast<C2 *>(C) + u * sC;
+    const bool rfast = SCAT && sc.mfast;
+    const int64_t mask = ((int64_t)1 << sc.shift) - 1;
+    const int nout = rows * N;
+    for (int o = tid; o < nout; o += 256) {
+        int r, n;
+        if (rfast) {
+            n = o / rows;
+            r = o - n * rows;
+        } else {
+            r = o / N;
+            n = o - r * N;
+        }
+        const C2 *ar = As + r * ld, *bn = Bs + n * ld;
+        R re = 0, im = 0;
+        for (int k = 0; k < K; ++k) {
+            const C2 x = ar[k], y = bn[k];
+            re += x.x * y.x - x.y * y.y;
+            im += x.x * y.y + x.y * y.x;
+        }
+        C2 v;
+        v.x = re;
+        v.y = im;
+        const int64_t row = m0 + r;
+        if constexpr (SCAT)
+            c[sc.fa[row >> sc.shift] + sc.fb[row & mask] + sc.fg[n]] = v;
+        else
+            c[row * N + n] = v;
+    }
+}
+
+// the general case: one thread per output element
 
 template <typename R, typename Acc>
 __global__ void k_small(const R *__restrict__ A, const R *__restrict__ Bt, R *__restrict__ C,
@@ -1105,7 +1166,38 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
 
 void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64_t M,
                     int64_t K, int64_t N, int64_t sA, int64_t sB, int64_t sC, int c64,
-                    void *stream) {
+                    void *stream, const ScatterStore *sc) {
+    const int64_t csize = c64 ? 8 : 16;
+    const hipStream_t st = (hipStream_t)stream;
+    if (units <= 0 || M <= 0 || N <= 0) return;
+    if (small_rows_fits(M, K, N, csize)) {
+        const int RB = (int)small_rows_block(K, csize);
+        const int64_t blocks = (M + RB - 1) / RB;
+        if (blocks >= ((int64_t)1 << 31)) fail(TNS_E_UNSUPPORTED, "small step with too many rows");
+        const ScatterStore none{};
+        for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+            const int64_t nu = std::min<int64_t>(65535, units - u0);
+            const dim3 grid((unsigned)blocks, (unsigned)nu);
+            if (c64) {
+                const float *a = (const float *)A + 2 * u0 * sA, *b = (const float *)Bt + 2 * u0 * sB;
+                float *c = (float *)C + 2 * u0 * sC;
+                if (sc) hipLaunchKernelGGL((k_small_rows<float, true>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                                           (int)N, RB, sA, sB, sC, *sc);
+                else hipLaunchKernelGGL((k_small_rows<float, false>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                                        (int)N, RB, sA, sB, sC, none);
+            } else {
+                const double *a = (const double *)A + 2 * u0 * sA, *b = (const double *)Bt + 2 * u0 * sB;
+                double *c = (double *)C + 2 * u0 * sC;
+                if (sc) hipLaunchKernelGGL((k_small_rows<double, true>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                                           (int)N, RB, sA, sB, sC, *sc);
+                else hipLaunchKernelGGL((k_small_rows<double, false>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                                        (int)N, RB, sA, sB, sC, none);
+            }
+            check_launch("small_contract");
+        }
+        return;
+    }
+    if (sc) fail(TNS_E_UNSUPPORTED, "internal: fused store on a small step outside the row kernel");
     const int64_t total = M * N * units;
     if (c64)
         hipLaunchKernelGGL((k_small<float, float>), dim3(grid_for(total, 256)), dim3(256), 0,

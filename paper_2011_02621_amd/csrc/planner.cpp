@@ -804,10 +804,12 @@ static void compile_steps(Plan &p) {
         p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
         p.steps.push_back(s);
     }
-    // a boundary permute after a GEMM step goes into that GEMM's store
+    // a boundary permute after a GEMM step, or after a small step that the
+    // row-tiled kernel takes, goes into that step's store
     for (size_t m = 2; m < p.steps.size(); ++m) {
         Step &s = p.steps[m], &prev = p.steps[m - 1];
-        if (!s.permute || prev.kernel != 0) continue;
+        if (!s.permute) continue;
+        if (prev.kernel != 0 && !(prev.kernel == 1 && small_rows_fits(prev.M, prev.K, prev.N, elem))) continue;
         if (build_scatter(s.perm, prev.M, prev.N, prev)) {
             s.permute_fused = true;
             prev.store_fused = true;

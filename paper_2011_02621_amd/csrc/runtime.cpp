@@ -380,7 +380,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                                  s.store_fused ? &p.scatter[m] : nullptr);
                 else if (s.kernel == 1)
                     launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
-                                           c64 ? 1 : 0, stream);
+                                           c64 ? 1 : 0, stream, s.store_fused ? &p.scatter[m] : nullptr);
                 else
                     launch::final_dot(src, Bb, partial + 2 * ug0, g, s.K, peak, s.K, c64 ? 1 : 0, stream);
                 ev_end();

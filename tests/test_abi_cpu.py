@@ -140,23 +140,38 @@ def test_plan_info_consistency(ctx):
     assert s == pytest.approx(i.path_score) and peak == i.peak_elems
 
 
-def test_permutes_fused_into_gemm_stores(ctx):
-    # a boundary permute after an MFMA GEMM step is done by that GEMM's store
-    c, _ = config("grid5x5_d10")
+def _small_rows_fits(m, k, n, csize):
+    # the row-tiled small-step kernel: at least 64 rows, 8 padded rows of A in
+    # 32 KiB and the padded B^T in 16 KiB of LDS
+    rb = min(256, 32768 // ((k + 1) * csize))
+    return m >= 64 and rb >= 8 and n * (k + 1) * csize <= 16384
+
+
+@pytest.mark.parametrize("workload", ["grid5x5_d10", "diag53_d12"])
+def test_permutes_fused_into_stores(ctx, workload):
+    # a boundary permute after an MFMA GEMM step, or after a small step that
+    # the row-tiled kernel takes, is done by that step's store
+    c, _ = config(workload, n_bits=1)
     for prec in ("c64", "c128"):
         i = ctx.plan(c, precision=prec).info()
+        elem = 16 if prec == "c128" else 8
         # the step arrays start at the first contraction (entry t is step t+1
-        # after the starting tensor); a fused permute needs a GEMM before it
+        # after the starting tensor)
         sp, k = np.asarray(i.step_permute), np.asarray(i.step_kernel)
+        m, kk, n = (np.asarray(a) for a in (i.step_m, i.step_k, i.step_n))
+        fusable = [k[t] == 0 or (k[t] == 1 and _small_rows_fits(m[t], kk[t], n[t], elem))
+                   for t in range(len(k))]
         assert (sp == 2).sum() > 0
         for t in np.nonzero(sp == 2)[0]:
-            assert t >= 1 and k[t - 1] == 0
+            assert t >= 1 and fusable[t - 1]
         for t in np.nonzero(sp == 1)[0]:
-            assert t == 0 or k[t - 1] != 0
+            assert t == 0 or not fusable[t - 1]
+        if workload == "diag53_d12":
+            # the large permutes there follow small steps
+            assert any(sp[t] == 2 and k[t - 1] == 1 for t in range(1, len(k)))
         # permute launches only (the permuted tensor holds M * K elements):
         # the fused ones are not counted
-        elem = 16 if prec == "c128" else 8
-        launched = sum(2.0 * elem * i.step_m[t] * i.step_k[t] for t in np.nonzero(sp == 1)[0])
+        launched = sum(2.0 * elem * m[t] * kk[t] for t in np.nonzero(sp == 1)[0])
         assert i.permute_bytes_per_amp == pytest.approx(launched * i.n_slices)
 
 

@@ -185,6 +185,42 @@ def test_grid5x5_d10(ctx, prec):
     say("grid5x5_d10", prec, "rel_l2 %.3e max_scaled %.3e f_xeb %.6f" % (m["rel_l2"], m["max_scaled"], m["f_xeb"]))
 
 
+def _row_kernel_steps(info, csize):
+    # small steps that the row-tiled kernel takes (at least 64 rows, 8 padded
+    # rows of A in 32 KiB, padded B^T in 16 KiB), and those whose store does
+    # the next step's permute
+    k, sp = np.asarray(info.step_kernel), np.asarray(info.step_permute)
+    rows = []
+    for t in range(len(k)):
+        m, kk, n = int(info.step_m[t]), int(info.step_k[t]), int(info.step_n[t])
+        rb = min(256, 32768 // ((kk + 1) * csize))
+        if k[t] == 1 and m >= 64 and rb >= 8 and n * (kk + 1) * csize <= 16384:
+            rows.append(t)
+    fused = [t for t in rows if t + 1 < len(k) and sp[t + 1] == 2]
+    return rows, fused
+
+
+@pytest.fixture(scope="module")
+def grid5x5_d8():
+    c = random_circuit(grid(5, 5), 8, 7)
+    bits = bitstrings(25, 64, 77)
+    return c, bits, sv.amplitudes(c, bits)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("split", [1, 2])
+def test_small_row_steps_grid5x5_d8(ctx, grid5x5_d8, prec, split):
+    # random 25-qubit circuit whose plan has small-bond steps of 64 .. 262144
+    # rows, several storing in the next step's order, against the oracle
+    c, bits, ref = grid5x5_d8
+    p = ctx.plan(c, precision=prec, split_cycle=split)
+    rows, fused = _row_kernel_steps(p.info(), 16 if prec == "c128" else 8)
+    say("grid5x5_d8 small steps", prec, split, "row steps", len(rows), "fused", len(fused))
+    assert len(rows) >= 4 and len(fused) >= 1
+    got = ctx.amplitudes(p, bits)
+    check(ref, got, c.n, prec)
+
+
 @pytest.mark.parametrize("prec", ["c64_bf16x6", "c64_bf16x3"])
 def test_grid3x4_split_bf16(ctx, small, prec):
     c, bits, ref = small
