@@ -123,10 +123,10 @@ struct ScatterStore {
     int mfast = 0;   // 1: consecutive rows are consecutive in the target, 0: columns
 };
 
-// LDS budget of the row-tiled small-step kernel: rows of A (padded by one
-// complex) in kSmallRowsA bytes, at least 8 of them, and B^T (N x K, padded
-// likewise) in kSmallRowsB.
-constexpr int64_t kSmallRowsA = 32768, kSmallRowsB = 16384;
+// LDS of the row-tiled small-step kernel, sized per launch: rows of A
+// (padded by one complex) in at most kSmallRowsA bytes, at least 8 of them,
+// and B^T (N x K, padded likewise) in at most kSmallRowsB.
+constexpr int64_t kSmallRowsA = 32768, kSmallRowsB = 32768;
 inline int64_t small_rows_block(int64_t K, int64_t csize) {
     const int64_t rb = kSmallRowsA / ((K + 1) * csize);
     return rb < 256 ? rb : 256;

@@ -492,6 +492,10 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
         int stage = 0;
         for (int k0 = 0; k0 < Kr; k0 += BK) {
             const bool more = k0 + BK < Kr, more2 = k0 + 2 * BK < Kr;
+            // compiler strategy that interleaves the MFMAs with the LDS reads:
+            // measured +1.3-1.6 % on the 128 x 256 FP32 tile, no gain or a
+            // loss on the other tiles and modes
+            if constexpr (MODE == 1 && BJ == 4) __builtin_amdgcn_iglp_opt(1);
             const ET *Ac = As(stage), *Bc = Bs(stage);
             frags(0, Ac, Bc, 0);
 #pragma unroll
@@ -663,6 +667,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
         int stage = 0;
         for (int k0 = 0; k0 < Kr; k0 += F64_BK) {
             const bool more = k0 + F64_BK < Kr, more2 = k0 + 2 * F64_BK < Kr;
+            // MFMA / LDS-read interleaving strategy of the compiler: measured
+            // +1.8-2.4 % on the 128 x 128 tile
+            if constexpr (BI == 4 && BJ == 4) __builtin_amdgcn_iglp_opt(1);
             v4d a[BI], b[BJ];
             frags(a, b, As[stage], Bs[stage]);
             mfmas(a, b, 0, 2);
@@ -734,9 +741,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
 // ---------------------------------------------------------------------------
 // small steps, C[u][m][n] = sum_k A[u][m][k] B[u][n][k] with a small K or N.
 // k_small_rows: a block copies RB consecutive rows of A (one unit, contiguous)
-// and all of B into LDS with coalesced complex loads (rows padded by one
-// complex against bank conflicts), then its threads produce the RB x N
-// outputs from LDS.  Outputs are stored row-major (consecutive threads,
+// and all of B into LDS (sized per launch) with coalesced complex loads (rows
+// padded by one complex against bank conflicts), then its threads produce the
+// RB x N outputs from LDS.  Outputs are stored row-major (consecutive threads,
 // consecutive addresses) or through the fused-store tables in the order in
 // which the target is contiguous.  HBM traffic: A and C once.
 template <typename R, bool SCAT>
@@ -744,12 +751,14 @@ __global__ __launch_bounds__(256) void k_small_rows(const R *__restrict__ A, con
                                                     R *__restrict__ C, int64_t M, int K, int N, int RB,
                                                     int64_t sA, int64_t sB, int64_t sC, ScatterStore sc) {
     using C2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
-    __shared__ C2 As[kSmallRowsA / sizeof(C2)];
-    __shared__ C2 Bs[kSmallRowsB / sizeof(C2)];
+    extern __shared__ __align__(16) unsigned char small_lds[];
+    const int ld = K + 1;
+    C2 *As = reinterpret_cast<C2 *>(small_lds);   // RB x ld
+    C2 *Bs = As + (int64_t)RB * ld;               // N x ld
     const int64_t u = blockIdx.y;
     const int64_t m0 = (int64_t)blockIdx.x * RB;
     const int rows = (int)(M - m0 < RB ? M - m0 : RB);
-    const int tid = threadIdx.x, ld = K + 1;
+    const int tid = threadIdx.x;
     const C2 *a = reinterpret_cast<const C2 *>(A) + u * sA + m0 * K;
     const C2 *b = reinterpret_cast<const C2 *>(Bt) + u * sB;
     const int na = rows * K, nb = N * K;
@@ -1173,6 +1182,7 @@ void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64
     if (small_rows_fits(M, K, N, csize)) {
         const int RB = (int)small_rows_block(K, csize);
         const int64_t blocks = (M + RB - 1) / RB;
+        const size_t lds = (size_t)(RB + N) * (K + 1) * csize;   // <= 64 KiB
         if (blocks >= ((int64_t)1 << 31)) fail(TNS_E_UNSUPPORTED, "small step with too many rows");
         const ScatterStore none{};
         for (int64_t u0 = 0; u0 < units; u0 += 65535) {
@@ -1181,16 +1191,16 @@ void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64
             if (c64) {
                 const float *a = (const float *)A + 2 * u0 * sA, *b = (const float *)Bt + 2 * u0 * sB;
                 float *c = (float *)C + 2 * u0 * sC;
-                if (sc) hipLaunchKernelGGL((k_small_rows<float, true>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                if (sc) hipLaunchKernelGGL((k_small_rows<float, true>), grid, dim3(256), lds, st, a, b, c, M, (int)K,
                                            (int)N, RB, sA, sB, sC, *sc);
-                else hipLaunchKernelGGL((k_small_rows<float, false>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                else hipLaunchKernelGGL((k_small_rows<float, false>), grid, dim3(256), lds, st, a, b, c, M, (int)K,
                                         (int)N, RB, sA, sB, sC, none);
             } else {
                 const double *a = (const double *)A + 2 * u0 * sA, *b = (const double *)Bt + 2 * u0 * sB;
                 double *c = (double *)C + 2 * u0 * sC;
-                if (sc) hipLaunchKernelGGL((k_small_rows<double, true>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                if (sc) hipLaunchKernelGGL((k_small_rows<double, true>), grid, dim3(256), lds, st, a, b, c, M, (int)K,
                                            (int)N, RB, sA, sB, sC, *sc);
-                else hipLaunchKernelGGL((k_small_rows<double, false>), grid, dim3(256), 0, st, a, b, c, M, (int)K,
+                else hipLaunchKernelGGL((k_small_rows<double, false>), grid, dim3(256), lds, st, a, b, c, M, (int)K,
                                         (int)N, RB, sA, sB, sC, none);
             }
             check_launch("small_contract");

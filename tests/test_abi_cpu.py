@@ -142,9 +142,9 @@ def test_plan_info_consistency(ctx):
 
 def _small_rows_fits(m, k, n, csize):
     # the row-tiled small-step kernel: at least 64 rows, 8 padded rows of A in
-    # 32 KiB and the padded B^T in 16 KiB of LDS
+    # 32 KiB and the padded B^T in 32 KiB of LDS
     rb = min(256, 32768 // ((k + 1) * csize))
-    return m >= 64 and rb >= 8 and n * (k + 1) * csize <= 16384
+    return m >= 64 and rb >= 8 and n * (k + 1) * csize <= 32768
 
 
 @pytest.mark.parametrize("workload", ["grid5x5_d10", "diag53_d12"])

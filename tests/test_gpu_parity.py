@@ -187,14 +187,14 @@ def test_grid5x5_d10(ctx, prec):
 
 def _row_kernel_steps(info, csize):
     # small steps that the row-tiled kernel takes (at least 64 rows, 8 padded
-    # rows of A in 32 KiB, padded B^T in 16 KiB), and those whose store does
+    # rows of A in 32 KiB, padded B^T in 32 KiB), and those whose store does
     # the next step's permute
     k, sp = np.asarray(info.step_kernel), np.asarray(info.step_permute)
     rows = []
     for t in range(len(k)):
         m, kk, n = int(info.step_m[t]), int(info.step_k[t]), int(info.step_n[t])
         rb = min(256, 32768 // ((kk + 1) * csize))
-        if k[t] == 1 and m >= 64 and rb >= 8 and n * (kk + 1) * csize <= 16384:
+        if k[t] == 1 and m >= 64 and rb >= 8 and n * (kk + 1) * csize <= 32768:
             rows.append(t)
     fused = [t for t in rows if t + 1 < len(k) and sp[t + 1] == 2]
     return rows, fused
