@@ -193,6 +193,10 @@ def bench_104(T, ctx, args, torch):
     return {"grid8x13_d8": out}
 
 
+class _Skip(Exception):
+    pass
+
+
 def bench_53(T, ctx, args, torch):
     """53-qubit diagonal lattice.  Depth 10: full amplitudes of random
     bitstrings and a correlated batch (the 12 qubits the path absorbs last are
@@ -213,6 +217,8 @@ def bench_53(T, ctx, args, torch):
 
     # ---- depth 10
     try:
+        if args.d12_only:
+            raise _Skip()
         c10 = random_circuit(diagonal53(), 10, 3)
         b10 = bitstrings(53, 64, 103)
         res = {}
@@ -257,6 +263,8 @@ def bench_53(T, ctx, args, torch):
         ps.close()
         out["diag53_d10"] = res
         print("[bench] diag53_d10 done", file=sys.stderr, flush=True)
+    except _Skip:
+        pass
     except Exception as e:
         out["diag53_d10"] = {"error": str(e)}
 
@@ -269,7 +277,10 @@ def bench_53(T, ctx, args, torch):
         res["plan_s"] = round(time.perf_counter() - t, 2)
         i53 = p64.info()
         oq = [int(q) for q in i53.path[-k_open:]]
-        for label, opts in (("single", {}), ("correlated_batch", {"open_qubits": oq})):
+        legs = [(label, opts) for label, opts in (("single", {}), ("correlated_batch", {"open_qubits": oq}))
+                if label in args.d12_legs.split(",")]
+        precs = args.d12_precisions.split(",")
+        for label, opts in legs:
             base = p64 if not opts else ctx.plan(c53, precision="c64", **opts)
             ib = base.info()
             same = dict(split_cycle=int(ib.split_cycle), path=ib.path.tolist(),
@@ -281,7 +292,7 @@ def bench_53(T, ctx, args, torch):
                  "n_slices": ns, "split": int(ib.split_cycle), "peak_elems": int(ib.peak_elems),
                  "slices_timed": nt}
             parts = {}
-            for prec in ("c64", "c64_bf16x3", "c128"):
+            for prec in precs:
                 plan = base if prec == "c64" else ctx.plan(c53, precision=prec, **same)
                 a, dt, st = timed(plan, b53, slices=(0, nt))
                 parts[prec] = a.reshape(-1)
@@ -295,7 +306,8 @@ def bench_53(T, ctx, args, torch):
                     plan.close()
                 print(f"[bench] diag53_d12 {label} {prec}: {dt / nt:.2f} s/slice", file=sys.stderr, flush=True)
             for prec in ("c64", "c64_bf16x3"):
-                r[prec]["partial_rel_l2_vs_c128"] = rel_l2(parts["c128"], parts[prec])
+                if prec in parts and "c128" in parts:
+                    r[prec]["partial_rel_l2_vs_c128"] = rel_l2(parts["c128"], parts[prec])
             if opts:
                 r["open_qubits"] = oq
                 base.close()
@@ -320,6 +332,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-d12", action="store_true", help="skip the 53-qubit depth-12 slice timing")
     ap.add_argument("--d12-slices", type=int, default=2)
+    ap.add_argument("--d12-only", action="store_true",
+                    help="time only the 53-qubit depth-12 slices (for kernel traces); prints that leg alone")
+    ap.add_argument("--d12-precisions", default="c64,c64_bf16x3,c128")
+    ap.add_argument("--d12-legs", default="single,correlated_batch")
     ap.add_argument("--no-104", action="store_true", help="skip the 104-qubit grid leg")
     ap.add_argument("--b104-bits", type=int, default=4, help="bitstrings timed on the 104-qubit grid")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -333,6 +349,14 @@ def main():
     import torch
     import paper_2011_02621_amd as T
     from circuits import config, random_circuit, diagonal53, bitstrings
+
+    if args.d12_only:
+        ctx = T.Context(0)
+        res = bench_53(T, ctx, args, torch)
+        print(json.dumps({"metric": "53-qubit depth-12 slice timing (partial contraction)", "n_gpus": 1,
+                          "data": "synthetic", **res}))
+        ctx.close()
+        return
 
     if args.copy_calibration:
         # a plain device copy of known size, for scaling HBM byte counters
