@@ -31,10 +31,11 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant GEMM, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (the summary and commands
 # are in profiles/gemm_f32_grid5x5_d10_traffic.md).  Keyed by the sha256
-# prefix of the kernel source the counters were taken on and by the plan
-# (split cycle, flops per amplitude): a change to either makes the entry
-# stale and the bench reports null.
-MEASURED_TRAFFIC = {("c64", "grid5x5_d10", "69613043caeb1b27", "split2:4.799972e+11"): 791.9 * 2 ** 20}
+# prefix of the kernel source the counters were taken on, by the plan (split
+# cycle, flops per amplitude) and by the algorithmic bytes per launch (units
+# per launch): a change to any of them makes the entry stale and the bench
+# reports null.
+MEASURED_TRAFFIC = {("c64", "grid5x5_d10", "69613043caeb1b27", "split2:4.799972e+11:5422MiB"): 6582.7 * 2 ** 20}
 
 
 def rel_l2(a, b):
@@ -404,7 +405,8 @@ def main():
     import hashlib
     src = os.path.join(ROOT, "paper_2011_02621_amd", "csrc", "kernels_contract.hip")
     src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    plan_key = f"split{info.split_cycle}:{info.flops_per_amp:.6e}"
+    alg_launch = agg["gemm_bytes"] / max(agg["gemm_launches"], 1)
+    plan_key = f"split{info.split_cycle}:{info.flops_per_amp:.6e}:{alg_launch / 2 ** 20:.0f}MiB"
     traffic = MEASURED_TRAFFIC.get((args.precision, args.workload, src_hash, plan_key))
     roofline = {"bound": "mfma", "kernel": kname,
                 "achieved": round(gemm_tflops, 3), "peak": PEAK_TFLOPS[args.precision],
