@@ -221,6 +221,19 @@ def test_small_row_steps_grid5x5_d8(ctx, grid5x5_d8, prec, split):
     check(ref, got, c.n, prec)
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_more_units_than_a_grid_dimension(ctx, small, prec):
+    # 70000 bitstrings of a 12-qubit plan: a launch carries up to 65536
+    # (bitstring x slice) units, beyond the 65535 blocks of a grid's y
+    # dimension, so every launcher has to split its units
+    c, _, _ = small
+    bits = bitstrings(c.n, 70000, 7)
+    say("grid3x4_d8 many units", prec, bits.shape)
+    ref = sv.amplitudes(c, bits)
+    got = ctx.amplitudes(ctx.plan(c, precision=prec), bits)
+    check(ref, got, c.n, prec)
+
+
 @pytest.mark.parametrize("prec", ["c64_bf16x6", "c64_bf16x3"])
 def test_grid3x4_split_bf16(ctx, small, prec):
     c, bits, ref = small
