@@ -1075,16 +1075,13 @@ static void launch_c64(int mode, dim3 grid, hipStream_t st, const float *A, cons
         else
             fail(TNS_E_UNSUPPORTED, "internal: no 128 x 256 tile for split-BF16 x6");
     } else {
-        // measured: on the 128 x 128 tile a k-step of 16 pays for short k-loops
-        // (2K < 1024), a k-step of 32 for long ones
+        // measured: on the 128 x 128 FP32 tile a k-step of 16 pays for short
+        // k-loops (2K < 1024), a k-step of 32 for long ones; split-BF16 x3
+        // measured best at 32 throughout
         if constexpr (S == 2) {
-            if (Kr < 1024 && (mode == 1 || mode == 2)) {
-                if (mode == 1)
-                    hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
-                                       Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
-                else
-                    hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 2, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
-                                       Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
+            if (Kr < 1024 && mode == 1) {
+                hipLaunchKernelGGL((k_gemm_c64<BI, BJ, WGM, WGN, 1, S, 16, SCAT>), grid, dim3(256), 0, st, A, B, C, M,
+                                   Kr, Nr, sA, sB, sC, tiles_n, sc, row0);
                 return;
             }
         }
@@ -1130,13 +1127,13 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
     // tile shape: complex64 256 x 32 for N <= 16 complex, 256 x 64 for N <= 32,
-    // else 128 x 128, or 128 x 256 for N >= 256 complex with split-BF16 x3
-    // (+5-8 %) or FP32 with 2K >= 1024 (+0.5-1 %; split-BF16 x6 loses there,
-    // its fragments leave one block per CU); complex128 128 x 128 for N >= 128
-    // complex and M >= 4096, else 64 x 64 (measured: the large tiles lose on
-    // narrow and short shapes)
+    // else 128 x 128, or 128 x 256 for split-BF16 x3 with N >= 128 complex
+    // (+5-8 %) and for FP32 with N >= 256 and 2K >= 1024 (+0.5-1 %; split-BF16
+    // x6 loses there, its fragments leave one block per CU); complex128
+    // 128 x 128 for N >= 128 complex and M >= 4096, else 64 x 64 (measured: the
+    // large tiles lose on narrow and short shapes)
     const bool f64_big = Nr >= 256 && M >= 4096;
-    const bool wide = Nr >= 512 && (mode == 2 || (mode == 1 && Kr >= 1024));
+    const bool wide = (mode == 2 && Nr >= 256) || (mode == 1 && Nr >= 512 && Kr >= 1024);
     const int shape = !c64 ? (f64_big ? 4 : 0) : (Nr <= 32 ? 1 : (Nr <= 64 ? 2 : (wide ? 5 : 3)));
     const int BM = shape == 0 ? 64 : (shape == 3 || shape == 4 || shape == 5 ? 128 : 256);
     const int BN = shape == 0 ? 64 : (shape == 1 ? 32 : (shape == 2 ? 64 : (shape == 5 ? 256 : 128)));
