@@ -312,6 +312,37 @@ def test_clifford_104_against_tableau(ctx, prec):
     assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 2 * tol * max(p_ref.max(), 2.0 ** -104)
 
 
+@pytest.fixture(scope="module")
+def diag53_d12_slice(ctx):
+    # complex128 partial sum over the first slice of the 53-qubit depth-12
+    # contraction, with the path and cuts the other precisions reuse
+    c, bits = config("diag53_d12", n_bits=1)
+    say("diag53_d12 c128 plan + one slice")
+    p = ctx.plan(c, precision="c128")
+    i = p.info()
+    same = dict(split_cycle=int(i.split_cycle), path=i.path.tolist(), cuts=i.cut_edges.tolist())
+    ref = ctx.amplitudes(p, bits, slices=(0, 1))
+    p.close()
+    return c, bits, same, ref, int(i.n_slices), int(i.peak_elems)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c64_bf16x6"])
+def test_diag53_d12_slice_against_c128(ctx, diag53_d12_slice, prec):
+    # the launch configuration the bench times at 53 qubits, depth 12 (256
+    # slices, 2^32-element intermediates); no oracle reaches this size, so
+    # the property checked is that one slice's partial sum agrees with the
+    # complex128 path on the same network to the complex64 tolerance
+    c, bits, same, ref, n_slices, peak = diag53_d12_slice
+    assert n_slices == 256 and peak == 1 << 32
+    say("diag53_d12", prec, "one slice")
+    p = ctx.plan(c, precision=prec, **same)
+    got = ctx.amplitudes(p, bits, slices=(0, 1))
+    p.close()
+    rel = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say("diag53_d12", prec, "rel %.3e" % rel)
+    assert rel <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_frugal_sampling(ctx, prec):
     # correlated batches of 2^3 candidates; decisions against the oracle's
