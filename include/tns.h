@@ -158,8 +158,11 @@ typedef struct {
     int64_t device_bytes_resident;  /* ket tensors and plan tables */
     int64_t device_bytes_per_unit;  /* workspace of one (bitstring, slice) unit */
     int32_t n_fused_ket, n_fused_bra;
-    int32_t search_complete;        /* Algorithm 1 finished within its budget */
-    int64_t search_states;          /* states popped by the path search */
+    int32_t search_complete;        /* 1 when every Algorithm 1 search behind the final path
+                                       finished within max_search_states (also 1 for a given
+                                       or greedy path); 0 when one stopped at the budget, whose
+                                       result is then the greedy path */
+    int64_t search_states;          /* states popped by those Algorithm 1 searches */
     int32_t max_rank_used;          /* rank bound M used by the search */
     double fidelity;                /* Eq. (9) with the paper's Sycamore error rates */
     double n_samples;               /* (3 / fidelity)^2 */

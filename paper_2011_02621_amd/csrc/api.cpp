@@ -362,8 +362,8 @@ tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
         o->device_bytes_per_unit = p->bytes_per_unit;
         o->n_fused_ket = p->n_fused_ket;
         o->n_fused_bra = p->n_fused_bra;
-        o->search_complete = p->path.complete ? 1 : 0;
-        o->search_states = p->path.states;
+        o->search_complete = p->search_complete ? 1 : 0;
+        o->search_states = p->search_states;
         o->max_rank_used = p->path.max_rank;
         o->fidelity = p->fidelity;
         o->n_samples = p->n_samples;

@@ -228,6 +228,10 @@ struct Plan {
 
     // path and steps
     PathResult path;
+    // Algorithm 1 searches that built the final path: all finished within
+    // their state budget, and the states they popped
+    bool search_complete = true;
+    int64_t search_states = 0;
     std::vector<Step> steps;
     int64_t peak_elems = 0;
     int64_t unit_stride = 0;             // boundary buffer stride per unit (peak, 32-aligned)

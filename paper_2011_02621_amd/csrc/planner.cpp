@@ -426,8 +426,9 @@ PathResult path_search(int n, const std::vector<std::pair<int, int>> &edges,
     if (mode != TNS_PATH_ALGORITHM1) fail(TNS_E_INVALID_ARG, "unknown path mode");
     int M = max_rank > 0 ? max_rank : gr.max_rank;
     double upper = assumptions ? gr.score : std::numeric_limits<double>::infinity();
-    PathResult r = algorithm1(g, M, assumptions, max_states > 0 ? max_states : 4000000, upper,
-                              assumptions ? &gr : nullptr);
+    // an exhausted state budget returns the greedy path, marked incomplete
+    // (with the assumptions off the search is exact and has no other bound)
+    PathResult r = algorithm1(g, M, assumptions, max_states > 0 ? max_states : 4000000, upper, &gr);
     r.max_rank = std::max(r.max_rank, 0);
     // report the rank bound actually used by the search
     if (assumptions) r.max_rank = M;
@@ -1040,9 +1041,16 @@ static void choose_cuts_and_path(Plan &p) {
             given.push_back(e);
         }
     }
+    p.search_complete = true;
+    p.search_states = 0;
     auto search = [&](const std::vector<double> &d, int mode) {
-        return path_search(c.n, E, d, mode, p.opts.max_rank, p.opts.path_assumptions != 0,
-                           p.opts.max_search_states);
+        PathResult r = path_search(c.n, E, d, mode, p.opts.max_rank, p.opts.path_assumptions != 0,
+                                   p.opts.max_search_states);
+        if (mode == TNS_PATH_ALGORITHM1) {
+            p.search_complete = p.search_complete && r.complete;
+            p.search_states += r.states;
+        }
+        return r;
     };
     if (p.opts.path) {
         PathResult r;

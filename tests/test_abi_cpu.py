@@ -254,3 +254,14 @@ def test_algorithm1_grid_beats_or_ties_greedy():
     _, s1 = T.path_search(g.n, g.edges, dims, mode="algorithm1")
     _, sg = T.path_search(g.n, g.edges, dims, mode="greedy")
     assert s1 <= sg
+
+
+def test_exhausted_exact_search_falls_back_to_greedy(ctx):
+    # Algorithm 1 without its assumptions and a tiny state budget: the plan
+    # keeps the greedy path and reports the search as incomplete
+    c, _ = config("grid3x4_d8")
+    i = ctx.plan(c, path_mode="algorithm1", path_assumptions=False, max_search_states=3).info()
+    g = ctx.plan(c, path_mode="greedy").info()
+    assert not i.search_complete
+    assert list(i.path) == list(g.path)
+    assert i.flops_per_amp == g.flops_per_amp
