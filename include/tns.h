@@ -140,7 +140,10 @@ typedef struct {
     const int64_t *step_m;          /* [n_steps] GEMM rows (open legs kept) */
     const int64_t *step_k;          /* [n_steps] shared-bond product */
     const int64_t *step_n;          /* [n_steps] new-leg product */
-    const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM, 1 small, 2 final dot */
+    const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM (real embedding), 1 small,
+                                       2 final dot, 3 MFMA GEMM in the three-multiplication
+                                       form (complex64 steps with even K >= 128, N >= 64,
+                                       M >= 64) */
     const int32_t *step_permute;    /* [n_steps] 0 no permute, 1 permute launch, 2 permute done
                                        by the previous step's store (fused; a GEMM, or a
                                        small-bond step with at least 64 rows) */
@@ -189,6 +192,10 @@ typedef struct {
     double ms_permute;              /* boundary permutes */
     double permute_bytes;           /* bytes read + written by them */
     double ms_small;                /* small-bond and final-dot steps */
+    double gemm_mfma_flops;         /* real flops the MFMA instructions of the GEMM launches
+                                       execute: 8 M K N for the real-embedded forms, 6 M K N
+                                       for the three-multiplication complex64 form, 3x or 6x
+                                       8 M K N (BF16) for split-BF16 */
 } tns_stats;
 
 /* --- context ---------------------------------------------------------- */

@@ -427,6 +427,7 @@ static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n,
             stats->ms_permute = rs.ms_permute;
             stats->permute_bytes = rs.permute_bytes;
             stats->ms_small = rs.ms_small;
+            stats->gemm_mfma_flops = rs.gemm_mfma_flops;
         }
     });
 }

@@ -132,6 +132,13 @@ inline int64_t small_rows_block(int64_t K, int64_t csize) {
     return rb < 256 ? rb : 256;
 }
 // csize: bytes per complex element (8 for complex64, 16 for complex128)
+// complex64 MFMA steps that take the three-multiplication GEMM (kernel
+// class 3): even K of at least 128 and at least 64 complex columns (its block
+// is 128 x 64); measured with fused stores: +12 % from K = 256 up, +2-7 % at
+// K = 128, a loss of 3-10 % at K <= 64 (the epilogue then dominates)
+inline bool gemm_3m_fits(int64_t M, int64_t K, int64_t N) {
+    return K % 2 == 0 && K >= 128 && N >= 64 && M >= 64;
+}
 inline bool small_rows_fits(int64_t M, int64_t K, int64_t N, int64_t csize) {
     return M >= 64 && small_rows_block(K, csize) >= 8 && N * (K + 1) * csize <= kSmallRowsB;
 }
@@ -304,7 +311,7 @@ struct RunStats {
     double flops = 0;
     int64_t units = 0, launches = 0;
     bool profile = false;            // time kernel classes with events
-    double ms_gemm = 0, gemm_flops = 0, gemm_bytes = 0;
+    double ms_gemm = 0, gemm_flops = 0, gemm_bytes = 0, gemm_mfma_flops = 0;
     int64_t gemm_launches = 0;
     double ms_permute = 0, permute_bytes = 0, ms_small = 0;
 };
@@ -357,7 +364,8 @@ void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_s
              int64_t slice0, int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream);
 // sc: when non-null, C is stored through the fused-store tables (the row
-// index includes every row of the unit, C is the unit's base)
+// index includes every row of the unit, C is the unit's base).  mode 4 (the
+// three-multiplication form) takes Bt as the plain complex [N][K].
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
           const ScatterStore *sc = nullptr);

@@ -237,6 +237,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
 // part products on the BF16 MFMA cores with FP32 accumulation:
 //   NSPLIT = 2: hi*hi + hi*mid + mid*hi                          (3 products)
 //   NSPLIT = 3: the same plus hi*lo + mid*mid + lo*hi            (6 products)
+typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
@@ -561,6 +562,154 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
                         stg[(i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + (lane & 31)] = acc[i][j][r];
+            });
+    }
+}
+
+// Complex64 GEMM in the three-multiplication form on FP32 MFMA:
+// C[M][N] = A[M][K] B[N][K]^T with A, B, C complex (interleaved re, im) and
+//   T0 = Ar Br^T, T1 = Ai Bi^T, T2 = (Ar + Ai)(Br + Bi)^T,
+//   Re C = T0 - T1, Im C = T2 - T0 - T1,
+// three real products of M x K x N instead of the four that the real
+// embedding of the other kernels multiplies (6 M K N flops instead of 8).
+// Loads read interleaved complex pairs; the LDS store writes the three planes
+// (re, im, re + im) of A and of B.  Four waves in 2 x 2, each owning 64 rows x
+// 32 complex columns (two 32 x 32 blocks per product), so the block is 128 x 64
+// complex; k-step 8 complex; the two-stage pipeline of k_gemm_c64 (next tile
+// in registers, stored to the other stage after the MFMAs, the tile after it
+// fetched right behind).  K is even (pairs never straddle the end of K).
+constexpr int M3_BKC = 8, M3_LD = M3_BKC + 4;   // complex k per tile, floats per plane row
+template <bool SCAT, bool FULLK>
+__global__ __launch_bounds__(256) void k_gemm_3m(const float *__restrict__ A, const float *__restrict__ B,
+                                                 float *__restrict__ C, int64_t M, int K, int N,
+                                                 int64_t sA, int64_t sB, int64_t sC, int tiles_n,
+                                                 ScatterStore sc, int64_t row0) {
+    constexpr int BI = 2, BM = 128, BN = 64, LD = M3_LD;
+    constexpr int APL = BM * LD, BPL = BN * LD, STG = 3 * (APL + BPL);
+    __shared__ float smem[2 * STG];
+    auto As = [&](int st, int p) { return smem + st * STG + p * APL; };
+    auto Bs = [&](int st, int p) { return smem + st * STG + 3 * APL + p * BPL; };
+    // a row's k-tile is 8 complex = 4 float4; 256 threads cover 64 rows per pass
+    constexpr int TPR = M3_BKC / 2, RPP = 256 / TPR, AV = BM / RPP, BV = BN / RPP;
+    const int64_t u = blockIdx.y;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+    const int64_t m0 = tm * BM;
+    const int n0 = (int)tn * BN;
+    A += 2 * u * sA;
+    B += 2 * u * sB;
+    C += 2 * u * sC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    v16f acc[3][BI];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[p][i][r] = 0.0f;
+    const int lrow = tid / TPR, lk = (tid % TPR) * 2;   // this thread's complex pair in the k-tile
+    // rows clamped into the operands (rows past M or N are never stored)
+    const float *ap[AV], *bp[BV];
+#pragma unroll
+    for (int i = 0; i < AV; ++i) ap[i] = A + 2 * (std::min<int64_t>(m0 + lrow + RPP * i, M - 1) * K + lk);
+#pragma unroll
+    for (int i = 0; i < BV; ++i) bp[i] = B + 2 * ((int64_t)std::min(n0 + lrow + RPP * i, N - 1) * K + lk);
+    v4f ra[AV], rb[BV];
+    auto fetch = [&](int k0) {
+        // FULLK (K a multiple of the k-step): no guard and no branch, which
+        // keeps the loads in the MFMAs' basic block (measured +10 %)
+        if (FULLK || k0 + M3_BKC <= K) {
+#pragma unroll
+            for (int i = 0; i < AV; ++i) ra[i] = *reinterpret_cast<const v4f *>(ap[i] + 2 * k0);
+#pragma unroll
+            for (int i = 0; i < BV; ++i) rb[i] = *reinterpret_cast<const v4f *>(bp[i] + 2 * k0);
+        } else {
+            const bool in = k0 + lk < K;   // K even: the pair is whole or absent
+#pragma unroll
+            for (int i = 0; i < AV; ++i) ra[i] = in ? *reinterpret_cast<const v4f *>(ap[i] + 2 * k0) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < BV; ++i) rb[i] = in ? *reinterpret_cast<const v4f *>(bp[i] + 2 * k0) : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto planes = [&](float *p0, float *p1, float *p2, int o, v4f x) {
+        *reinterpret_cast<v2f *>(p0 + o) = v2f{x[0], x[2]};
+        *reinterpret_cast<v2f *>(p1 + o) = v2f{x[1], x[3]};
+        *reinterpret_cast<v2f *>(p2 + o) = v2f{x[0] + x[1], x[2] + x[3]};
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) planes(As(st, 0), As(st, 1), As(st, 2), (lrow + RPP * i) * LD + lk, ra[i]);
+#pragma unroll
+        for (int i = 0; i < BV; ++i) planes(Bs(st, 0), Bs(st, 1), Bs(st, 2), (lrow + RPP * i) * LD + lk, rb[i]);
+    };
+    // lanes 0-31 / 32-63 take k-slots 0 / 1 of an MFMA: k = 4 * slot + t for
+    // the four MFMAs t of the tile, one 16-byte LDS read per plane and block
+    const int arow = (wm * BI * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
+    const int brow = (wn * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
+    const int nt = (K + M3_BKC - 1) / M3_BKC;
+    fetch(0);
+    stash(0);
+    if (nt > 1) fetch(M3_BKC);
+    __syncthreads();
+    int st = 0;
+    for (int t = 0; t < nt; ++t) {
+        v4f fa[3][BI], fb[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int i = 0; i < BI; ++i) fa[p][i] = *reinterpret_cast<const v4f *>(As(st, p) + arow + i * 32 * LD);
+            fb[p] = *reinterpret_cast<const v4f *>(Bs(st, p) + brow);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int i = 0; i < BI; ++i)
+                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[p][i][q], fb[p][q], acc[p][i], 0, 0, 0);
+        if (t + 1 < nt) {
+            // the other stage was last read in tile t-1, before the previous barrier
+            stash(st ^ 1);
+            if (t + 2 < nt) fetch((t + 2) * M3_BKC);
+        }
+        __syncthreads();
+        st ^= 1;
+    }
+    // 32x32 accumulator layout: lane holds complex column lane%32 of its block
+    // and rows 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r
+    if constexpr (!SCAT) {
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 32 + (lane & 31);
+                const float t0 = acc[0][i][r], t1 = acc[1][i][r], t2 = acc[2][i][r];
+                if (row < M && col < N)
+                    *reinterpret_cast<v2f *>(C + 2 * (row * N + col)) = v2f{t0 - t1, t2 - t0 - t1};
+            }
+    } else {
+        // fused store staged per wave through LDS (free after the last
+        // barrier), in two slices of 16 complex columns: lanes whose column
+        // falls in slice j stage their values, then every lane stores whole
+        // complex values in the order in which the target is contiguous
+        constexpr int WR = BI * 32, SLD = 34;
+        static_assert(4 * WR * SLD <= 2 * STG, "staging fits in the stages");
+        float *stg = smem + wave * WR * SLD;
+        const int hc = lane & 31, half = hc >> 4;
+        fused_store_wave<float2, WR, 16, SLD, 2>(
+            C, stg, sc, row0, m0 + wm * WR, M, 2 * (n0 + wn * 32), 2 * N, lane, [&](int j) {
+                if (half != j) return;
+#pragma unroll
+                for (int i = 0; i < BI; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float t0 = acc[0][i][r], t1 = acc[1][i][r], t2 = acc[2][i][r];
+                        *reinterpret_cast<v2f *>(
+                            &stg[(i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + 2 * (hc - 16 * j)]) =
+                            v2f{t0 - t1, t2 - t0 - t1};
+                    }
             });
     }
 }
@@ -1121,8 +1270,44 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
           const ScatterStore *sc) {
     // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
-    // split-BF16 MFMA with 3 / 6 products.  Strides arrive in complex elements;
-    // the kernels index reals.
+    // split-BF16 MFMA with 3 / 6 products, 4 complex64 in the three-
+    // multiplication form (FP32 MFMA; Bt is then the plain complex [N][K], not
+    // its real embedding).  Strides arrive in complex elements; the kernels
+    // index reals.
+    const hipStream_t st = (hipStream_t)stream;
+    if (mode == 4) {
+        if (K % 2 != 0) fail(TNS_E_UNSUPPORTED, "three-multiplication GEMM needs an even K");
+        if (units <= 0 || M <= 0 || N <= 0) return;
+        const int tiles_n = (int)((N + 63) / 64);
+        const int64_t rows_per = (((int64_t)1 << 30) / tiles_n) * 128;
+        for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+            const int64_t nu = std::min<int64_t>(65535, units - u0);
+            for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
+                const int64_t mr = std::min<int64_t>(rows_per, M - r0);
+                const dim3 grid((unsigned)(((mr + 127) / 128) * tiles_n), (unsigned)nu);
+                const int64_t crow = sc ? 0 : r0;
+                const float *a = (const float *)A + 2 * (u0 * sA + r0 * K);
+                const float *b = (const float *)Bt + 2 * u0 * sB;
+                float *c = (float *)C + 2 * (u0 * sC + crow * N);
+                const ScatterStore none{};
+                const bool full = K % M3_BKC == 0;
+                if (sc && full)
+                    hipLaunchKernelGGL((k_gemm_3m<true, true>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                       sA, sB, sC, tiles_n, *sc, r0);
+                else if (sc)
+                    hipLaunchKernelGGL((k_gemm_3m<true, false>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                       sA, sB, sC, tiles_n, *sc, r0);
+                else if (full)
+                    hipLaunchKernelGGL((k_gemm_3m<false, true>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                       sA, sB, sC, tiles_n, none, (int64_t)0);
+                else
+                    hipLaunchKernelGGL((k_gemm_3m<false, false>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                       sA, sB, sC, tiles_n, none, (int64_t)0);
+                check_launch("gemm_3m");
+            }
+        }
+        return;
+    }
     const int c64 = mode != 0;
     const int Kr = (int)(2 * K), Nr = (int)(2 * N);
     if (c64 && (Kr % 4) != 0) fail(TNS_E_UNSUPPORTED, "FP32 GEMM needs an even K");
@@ -1141,7 +1326,6 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     // rows per launch so that the grid stays below 2^31 blocks
     const int64_t max_tiles_m = ((int64_t)1 << 30) / tiles_n;
     const int64_t rows_per = max_tiles_m * BM;
-    const hipStream_t st = (hipStream_t)stream;
     for (int64_t u0 = 0; u0 < units; u0 += 65535) {
         const int64_t nu = std::min<int64_t>(65535, units - u0);
         for (int64_t r0 = 0; r0 < M; r0 += rows_per) {

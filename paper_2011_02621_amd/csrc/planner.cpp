@@ -791,7 +791,8 @@ static void compile_steps(Plan &p) {
         } else if (last && s.M * s.N != ((int64_t)1 << c.n_open)) {
             fail(TNS_E_BAD_PATH, "internal: final tensor does not hold the open legs");
         } else if (s.K >= 16 && s.N >= 16 && s.M >= 16 && s.K % 2 == 0) {
-            s.kernel = 0;
+            // complex64 wide steps: three real products instead of four
+            s.kernel = (p.precision == TNS_C64 && gemm_3m_fits(s.M, s.K, s.N)) ? 3 : 0;
         } else {
             s.kernel = 1;
         }
@@ -805,12 +806,14 @@ static void compile_steps(Plan &p) {
         p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
         p.steps.push_back(s);
     }
-    // a boundary permute after a GEMM step, or after a small step that the
-    // row-tiled kernel takes, goes into that step's store
+    // a boundary permute after a GEMM step (either form), or after a small
+    // step that the row-tiled kernel takes, goes into that step's store
     for (size_t m = 2; m < p.steps.size(); ++m) {
         Step &s = p.steps[m], &prev = p.steps[m - 1];
         if (!s.permute) continue;
-        if (prev.kernel != 0 && !(prev.kernel == 1 && small_rows_fits(prev.M, prev.K, prev.N, elem))) continue;
+        if (prev.kernel != 0 && prev.kernel != 3 &&
+            !(prev.kernel == 1 && small_rows_fits(prev.M, prev.K, prev.N, elem)))
+            continue;
         if (build_scatter(s.perm, prev.M, prev.N, prev)) {
             s.permute_fused = true;
             prev.store_fused = true;

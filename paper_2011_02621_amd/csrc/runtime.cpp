@@ -333,14 +333,14 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
         char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
         // optional per-class timing: events recorded around launches on this stream
-        struct Ev { hipEvent_t a, b; int cls; double flops, bytes; };
+        struct Ev { hipEvent_t a, b; int cls; double flops, bytes, mfma; };
         std::vector<Ev> evs;
-        auto ev_begin = [&](int cls, double fl, double by) {
+        auto ev_begin = [&](int cls, double fl, double by, double mfma = 0) {
             if (!st.profile) return;
             Ev e{};
             (void)hipEventCreate(&e.a);
             (void)hipEventCreate(&e.b);
-            e.cls = cls; e.flops = fl; e.bytes = by;
+            e.cls = cls; e.flops = fl; e.bytes = by; e.mfma = mfma;
             (void)hipEventRecord(e.a, (hipStream_t)stream);
             evs.push_back(e);
         };
@@ -371,14 +371,25 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     st.launches += 1;
                 }
                 char *dst = (src == X) ? Y : X;
+                // the real-embedded GEMM takes B as its real embedding, the
+                // three-multiplication GEMM and the small kernels as plain complex
                 launch::build_b(site_ptr[s.site], Bb, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
                                 p.slice_map[s.site],
                                 s.bgather, s.K, s.N, c64 ? 1 : 0, s.kernel == 0 ? 1 : 0, stream);
                 const double mkn = (double)s.M * s.K * s.N * g;
                 const double by = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
-                ev_begin(s.kernel == 0 ? 0 : 2, 8.0 * mkn, by);
+                const bool is_gemm = s.kernel == 0 || s.kernel == 3;
+                // real flops the MFMA instructions execute: 8 M K N for the real
+                // embedding, 6 M K N for the three-multiplication form, times the
+                // number of products of a split-BF16 form
+                const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
+                                    : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
+                ev_begin(is_gemm ? 0 : 2, 8.0 * mkn, by, (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
                     launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream,
+                                 s.store_fused ? &p.scatter[m] : nullptr);
+                else if (s.kernel == 3)
+                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, 4, stream,
                                  s.store_fused ? &p.scatter[m] : nullptr);
                 else if (s.kernel == 1)
                     launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
@@ -402,7 +413,13 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         for (Ev &e : evs) {
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e.a, e.b);
-            if (e.cls == 0) { st.ms_gemm += ms; st.gemm_flops += e.flops; st.gemm_bytes += e.bytes; st.gemm_launches++; }
+            if (e.cls == 0) {
+                st.ms_gemm += ms;
+                st.gemm_flops += e.flops;
+                st.gemm_bytes += e.bytes;
+                st.gemm_mfma_flops += e.mfma;
+                st.gemm_launches++;
+            }
             else if (e.cls == 1) { st.ms_permute += ms; st.permute_bytes += e.bytes; }
             else st.ms_small += ms;
             (void)hipEventDestroy(e.a);

@@ -149,8 +149,8 @@ def _small_rows_fits(m, k, n, csize):
 
 @pytest.mark.parametrize("workload", ["grid5x5_d10", "diag53_d12"])
 def test_permutes_fused_into_stores(ctx, workload):
-    # a boundary permute after an MFMA GEMM step, or after a small step that
-    # the row-tiled kernel takes, is done by that step's store
+    # a boundary permute after an MFMA GEMM step (either form), or after a
+    # small step that the row-tiled kernel takes, is done by that step's store
     c, _ = config(workload, n_bits=1)
     for prec in ("c64", "c128"):
         i = ctx.plan(c, precision=prec).info()
@@ -159,8 +159,12 @@ def test_permutes_fused_into_stores(ctx, workload):
         # after the starting tensor)
         sp, k = np.asarray(i.step_permute), np.asarray(i.step_kernel)
         m, kk, n = (np.asarray(a) for a in (i.step_m, i.step_k, i.step_n))
-        fusable = [k[t] == 0 or (k[t] == 1 and _small_rows_fits(m[t], kk[t], n[t], elem))
+        fusable = [k[t] in (0, 3) or (k[t] == 1 and _small_rows_fits(m[t], kk[t], n[t], elem))
                    for t in range(len(k))]
+        # complex64 wide steps take the three-multiplication GEMM (class 3)
+        wide = [t for t in range(len(k))
+                if k[t] in (0, 3) and kk[t] % 2 == 0 and kk[t] >= 128 and n[t] >= 64 and m[t] >= 64]
+        assert all(k[t] == (3 if prec == "c64" else 0) for t in wide)
         assert (sp == 2).sum() > 0
         for t in np.nonzero(sp == 2)[0]:
             assert t >= 1 and fusable[t - 1]
