@@ -574,17 +574,18 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 // embedding of the other kernels multiplies (6 M K N flops instead of 8).
 // Loads read interleaved complex pairs; the LDS store writes the three planes
 // (re, im, re + im) of A and of B.  Four waves in 2 x 2, each owning 64 rows x
-// 32 complex columns (two 32 x 32 blocks per product), so the block is 128 x 64
-// complex; k-step 8 complex; the two-stage pipeline of k_gemm_c64 (next tile
-// in registers, stored to the other stage after the MFMAs, the tile after it
-// fetched right behind).  K is even (pairs never straddle the end of K).
+// 32 BJ complex columns (2 BJ blocks of 32 x 32 per product), so the block is
+// 128 x 64 BJ complex; k-step 8 complex; two LDS stages with the next tile in
+// registers and the tile after it fetched right behind, one barrier per tile
+// placed half-way through its MFMAs, and double-buffered fragments (see the
+// loop).  K is even (pairs never straddle the end of K).
 constexpr int M3_BKC = 8, M3_LD = M3_BKC + 4;   // complex k per tile, floats per plane row
-template <bool SCAT, bool FULLK>
-__global__ __launch_bounds__(256) void k_gemm_3m(const float *__restrict__ A, const float *__restrict__ B,
+template <bool SCAT, bool FULLK, int BJ>
+__global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *__restrict__ A, const float *__restrict__ B,
                                                  float *__restrict__ C, int64_t M, int K, int N,
                                                  int64_t sA, int64_t sB, int64_t sC, int tiles_n,
                                                  ScatterStore sc, int64_t row0) {
-    constexpr int BI = 2, BM = 128, BN = 64, LD = M3_LD;
+    constexpr int BI = 2, BM = 128, BN = 64 * BJ, LD = M3_LD;
     constexpr int APL = BM * LD, BPL = BN * LD, STG = 3 * (APL + BPL);
     __shared__ float smem[2 * STG];
     auto As = [&](int st, int p) { return smem + st * STG + p * APL; };
@@ -601,13 +602,15 @@ __global__ __launch_bounds__(256) void k_gemm_3m(const float *__restrict__ A, co
     C += 2 * u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    v16f acc[3][BI];
+    v16f acc[3][BI][BJ];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int i = 0; i < BI; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[p][i][r] = 0.0f;
+            for (int j = 0; j < BJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.0f;
     const int lrow = tid / TPR, lk = (tid % TPR) * 2;   // this thread's complex pair in the k-tile
     // rows clamped into the operands (rows past M or N are never stored)
     const float *ap[AV], *bp[BV];
@@ -643,73 +646,101 @@ __global__ __launch_bounds__(256) void k_gemm_3m(const float *__restrict__ A, co
 #pragma unroll
         for (int i = 0; i < BV; ++i) planes(Bs(st, 0), Bs(st, 1), Bs(st, 2), (lrow + RPP * i) * LD + lk, rb[i]);
     };
-    // lanes 0-31 / 32-63 take k-slots 0 / 1 of an MFMA: k = 4 * slot + t for
-    // the four MFMAs t of the tile, one 16-byte LDS read per plane and block
+    // lanes 0-31 / 32-63 take k-slots 0 / 1 of an MFMA: k = 4 * slot + q for
+    // the four MFMAs q of the tile, one 16-byte LDS read per plane and block
     const int arow = (wm * BI * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
-    const int brow = (wn * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
+    const int brow = (wn * BJ * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
+    v4f fa[2][3][BI], fb[2][3][BJ];
+    auto frags = [&](int buf, int st) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int i = 0; i < BI; ++i) fa[buf][p][i] = *reinterpret_cast<const v4f *>(As(st, p) + arow + i * 32 * LD);
+#pragma unroll
+            for (int j = 0; j < BJ; ++j) fb[buf][p][j] = *reinterpret_cast<const v4f *>(Bs(st, p) + brow + j * 32 * LD);
+        }
+    };
+    auto mfmas = [&](int buf, int q) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int i = 0; i < BI; ++i)
+#pragma unroll
+                for (int j = 0; j < BJ; ++j)
+                    acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[buf][p][i][q], fb[buf][p][j][q], acc[p][i][j], 0, 0, 0);
+    };
     const int nt = (K + M3_BKC - 1) / M3_BKC;
     fetch(0);
     stash(0);
     if (nt > 1) fetch(M3_BKC);
     __syncthreads();
-    int st = 0;
-    for (int t = 0; t < nt; ++t) {
-        v4f fa[3][BI], fb[3];
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-#pragma unroll
-            for (int i = 0; i < BI; ++i) fa[p][i] = *reinterpret_cast<const v4f *>(As(st, p) + arow + i * 32 * LD);
-            fb[p] = *reinterpret_cast<const v4f *>(Bs(st, p) + brow);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int i = 0; i < BI; ++i)
-                    acc[p][i] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[p][i][q], fb[p][q], acc[p][i], 0, 0, 0);
+    frags(0, 0);
+    // Tile t (fragments in registers, buffer t % 2): half of its MFMAs, then
+    // tile t+1 from registers into the other stage (last read for tile t-1,
+    // before the previous barrier), the fetch of tile t+2, the barrier, and
+    // tile t+1's fragments read from LDS while the second half of tile t's
+    // MFMAs runs, so no LDS latency sits between a barrier and the next MFMA.
+    auto body = [&](int t, int buf) {
+        const int st = t & 1;
+        mfmas(buf, 0);
+        mfmas(buf, 1);
         if (t + 1 < nt) {
-            // the other stage was last read in tile t-1, before the previous barrier
             stash(st ^ 1);
             if (t + 2 < nt) fetch((t + 2) * M3_BKC);
+            __syncthreads();
+            frags(buf ^ 1, st ^ 1);
         }
-        __syncthreads();
-        st ^= 1;
+        mfmas(buf, 2);
+        mfmas(buf, 3);
+    };
+    int t = 0;
+    for (; t + 1 < nt; t += 2) {   // two tiles per trip: static fragment buffers
+        body(t, 0);
+        body(t + 1, 1);
     }
+    if (t < nt) body(t, 0);
+    __syncthreads();   // the stages are reused for the store
     // 32x32 accumulator layout: lane holds complex column lane%32 of its block
     // and rows 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r
     if constexpr (!SCAT) {
 #pragma unroll
         for (int i = 0; i < BI; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int col = n0 + wn * 32 + (lane & 31);
-                const float t0 = acc[0][i][r], t1 = acc[1][i][r], t2 = acc[2][i][r];
-                if (row < M && col < N)
-                    *reinterpret_cast<v2f *>(C + 2 * (row * N + col)) = v2f{t0 - t1, t2 - t0 - t1};
-            }
+            for (int j = 0; j < BJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t row = m0 + wm * BI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int col = n0 + wn * BJ * 32 + j * 32 + (lane & 31);
+                    const float t0 = acc[0][i][j][r], t1 = acc[1][i][j][r], t2 = acc[2][i][j][r];
+                    if (row < M && col < N)
+                        *reinterpret_cast<v2f *>(C + 2 * (row * N + col)) = v2f{t0 - t1, t2 - t0 - t1};
+                }
     } else {
         // fused store staged per wave through LDS (free after the last
-        // barrier), in two slices of 16 complex columns: lanes whose column
+        // barrier), in 2 BJ slices of 16 complex columns: lanes whose column
         // falls in slice j stage their values, then every lane stores whole
         // complex values in the order in which the target is contiguous
         constexpr int WR = BI * 32, SLD = 34;
         static_assert(4 * WR * SLD <= 2 * STG, "staging fits in the stages");
         float *stg = smem + wave * WR * SLD;
         const int hc = lane & 31, half = hc >> 4;
-        fused_store_wave<float2, WR, 16, SLD, 2>(
-            C, stg, sc, row0, m0 + wm * WR, M, 2 * (n0 + wn * 32), 2 * N, lane, [&](int j) {
-                if (half != j) return;
+        fused_store_wave<float2, WR, 16, SLD, 2 * BJ>(
+            C, stg, sc, row0, m0 + wm * WR, M, 2 * (n0 + wn * BJ * 32), 2 * N, lane, [&](int s) {
+                if (half != (s & 1)) return;
+                const int jb = s >> 1;
 #pragma unroll
-                for (int i = 0; i < BI; ++i)
+                for (int j = 0; j < BJ; ++j) {
+                    if (j != jb) continue;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const float t0 = acc[0][i][r], t1 = acc[1][i][r], t2 = acc[2][i][r];
-                        *reinterpret_cast<v2f *>(
-                            &stg[(i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + 2 * (hc - 16 * j)]) =
-                            v2f{t0 - t1, t2 - t0 - t1};
-                    }
+                    for (int i = 0; i < BI; ++i)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const float t0 = acc[0][i][j][r], t1 = acc[1][i][j][r], t2 = acc[2][i][j][r];
+                            *reinterpret_cast<v2f *>(
+                                &stg[(i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + 2 * (hc - 16 * (s & 1))]) =
+                                v2f{t0 - t1, t2 - t0 - t1};
+                        }
+                }
             });
     }
 }
@@ -1266,6 +1297,43 @@ static void launch_f64(dim3 grid, hipStream_t st, const double *A, const double 
                            tiles_n, ScatterStore{}, (int64_t)0);
 }
 
+// Three-multiplication launches: BJ column blocks of 32 complex per wave (a
+// block of 128 x 64 BJ complex), chunked so that one launch holds at most 2^30
+// tiles per unit row range and 65535 units.
+template <int BJ>
+void launch_3m(const float *A, const float *Bt, float *C, int64_t units, int64_t M, int64_t K, int64_t N,
+               int64_t sA, int64_t sB, int64_t sC, hipStream_t st, const ScatterStore *sc) {
+    constexpr int BN = 64 * BJ;
+    const int tiles_n = (int)((N + BN - 1) / BN);
+    const int64_t rows_per = (((int64_t)1 << 30) / tiles_n) * 128;
+    const bool full = K % M3_BKC == 0;
+    const ScatterStore none{};
+    for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+        const int64_t nu = std::min<int64_t>(65535, units - u0);
+        for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
+            const int64_t mr = std::min<int64_t>(rows_per, M - r0);
+            const dim3 grid((unsigned)(((mr + 127) / 128) * tiles_n), (unsigned)nu);
+            const int64_t crow = sc ? 0 : r0;
+            const float *a = A + 2 * (u0 * sA + r0 * K);
+            const float *b = Bt + 2 * u0 * sB;
+            float *c = C + 2 * (u0 * sC + crow * N);
+            if (sc && full)
+                hipLaunchKernelGGL((k_gemm_3m<true, true, BJ>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, tiles_n, *sc, r0);
+            else if (sc)
+                hipLaunchKernelGGL((k_gemm_3m<true, false, BJ>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, tiles_n, *sc, r0);
+            else if (full)
+                hipLaunchKernelGGL((k_gemm_3m<false, true, BJ>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, tiles_n, none, (int64_t)0);
+            else
+                hipLaunchKernelGGL((k_gemm_3m<false, false, BJ>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, tiles_n, none, (int64_t)0);
+            check_launch("gemm_3m");
+        }
+    }
+}
+
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
           const ScatterStore *sc) {
@@ -1278,34 +1346,9 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     if (mode == 4) {
         if (K % 2 != 0) fail(TNS_E_UNSUPPORTED, "three-multiplication GEMM needs an even K");
         if (units <= 0 || M <= 0 || N <= 0) return;
-        const int tiles_n = (int)((N + 63) / 64);
-        const int64_t rows_per = (((int64_t)1 << 30) / tiles_n) * 128;
-        for (int64_t u0 = 0; u0 < units; u0 += 65535) {
-            const int64_t nu = std::min<int64_t>(65535, units - u0);
-            for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
-                const int64_t mr = std::min<int64_t>(rows_per, M - r0);
-                const dim3 grid((unsigned)(((mr + 127) / 128) * tiles_n), (unsigned)nu);
-                const int64_t crow = sc ? 0 : r0;
-                const float *a = (const float *)A + 2 * (u0 * sA + r0 * K);
-                const float *b = (const float *)Bt + 2 * u0 * sB;
-                float *c = (float *)C + 2 * (u0 * sC + crow * N);
-                const ScatterStore none{};
-                const bool full = K % M3_BKC == 0;
-                if (sc && full)
-                    hipLaunchKernelGGL((k_gemm_3m<true, true>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
-                                       sA, sB, sC, tiles_n, *sc, r0);
-                else if (sc)
-                    hipLaunchKernelGGL((k_gemm_3m<true, false>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
-                                       sA, sB, sC, tiles_n, *sc, r0);
-                else if (full)
-                    hipLaunchKernelGGL((k_gemm_3m<false, true>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
-                                       sA, sB, sC, tiles_n, none, (int64_t)0);
-                else
-                    hipLaunchKernelGGL((k_gemm_3m<false, false>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
-                                       sA, sB, sC, tiles_n, none, (int64_t)0);
-                check_launch("gemm_3m");
-            }
-        }
+        // BJ = 2 (128 x 128 complex, one wave per SIMD) measured level with or
+        // up to 10 % behind BJ = 1 (two waves per SIMD) on every step shape
+        launch_3m<1>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
         return;
     }
     const int c64 = mode != 0;
