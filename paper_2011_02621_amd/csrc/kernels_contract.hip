@@ -680,25 +680,35 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
     // before the previous barrier), the fetch of tile t+2, the barrier, and
     // tile t+1's fragments read from LDS while the second half of tile t's
     // MFMAs runs, so no LDS latency sits between a barrier and the next MFMA.
+    // The body has no branch (the last tile is peeled off and the fetch past
+    // it reads the last tile again), so the compiler schedules the stores and
+    // loads among the MFMAs of the whole stretch between two barriers.
     auto body = [&](int t, int buf) {
         const int st = t & 1;
         mfmas(buf, 0);
         mfmas(buf, 1);
-        if (t + 1 < nt) {
-            stash(st ^ 1);
-            if (t + 2 < nt) fetch((t + 2) * M3_BKC);
-            __syncthreads();
-            frags(buf ^ 1, st ^ 1);
-        }
+        stash(st ^ 1);
+        fetch(std::min(t + 2, nt - 1) * M3_BKC);
+        __syncthreads();
+        frags(buf ^ 1, st ^ 1);
         mfmas(buf, 2);
         mfmas(buf, 3);
     };
+    auto last = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mfmas(buf, q);
+    };
     int t = 0;
-    for (; t + 1 < nt; t += 2) {   // two tiles per trip: static fragment buffers
+    for (; t + 2 < nt; t += 2) {   // two tiles per trip: static fragment buffers
         body(t, 0);
         body(t + 1, 1);
     }
-    if (t < nt) body(t, 0);
+    if (t + 1 < nt) {
+        body(t, 0);
+        last(1);
+    } else {
+        last(0);
+    }
     __syncthreads();   // the stages are reused for the store
     // 32x32 accumulator layout: lane holds complex column lane%32 of its block
     // and rows 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r
