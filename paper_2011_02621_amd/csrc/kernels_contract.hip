@@ -265,6 +265,15 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
 // which the target is contiguous.  64 is a multiple of WR and of CW, so a
 // lane keeps one row (row order) or one column (column order) across its
 // stores, and the table lookups of that index are made once.
+// Orders one wave's LDS stores before its own later LDS loads (and the loads
+// before its next stores): the staging area of the fused store is private to
+// the wave, so no block barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename V, int WR, int CW, int SLD, int BJ, typename R, typename Stage>
 __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, const ScatterStore &sc,
                                                  int64_t row0, int64_t rbase, int64_t M, int cbase0,
@@ -284,7 +293,7 @@ __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, cons
 #pragma unroll
         for (int j = 0; j < BJ; ++j) {
             stage(j);
-            __syncthreads();
+            wave_sync();
             const int cb = cbase0 + j * 2 * CW;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
@@ -294,7 +303,7 @@ __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, cons
                     *reinterpret_cast<V *>(C + 2 * (ro + sc.fg[col >> 1])) =
                         *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
             }
-            __syncthreads();
+            wave_sync();
         }
     } else {
         const int lc = lane % CW;
@@ -304,7 +313,7 @@ __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, cons
 #pragma unroll
         for (int j = 0; j < BJ; ++j) {
             stage(j);
-            __syncthreads();
+            wave_sync();
             const int col = cbase0 + j * 2 * CW + 2 * lc;
             const int64_t co = col < Nr ? sc.fg[col >> 1] : -1;
 #pragma unroll
@@ -313,7 +322,7 @@ __device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, cons
                 if (ro[k] >= 0 && co >= 0)
                     *reinterpret_cast<V *>(C + 2 * (ro[k] + co)) = *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
             }
-            __syncthreads();
+            wave_sync();
         }
     }
 }
