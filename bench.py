@@ -313,8 +313,8 @@ def bench_53(T, ctx, args, torch):
                 if plan is not base:
                     plan.close()
                 print(f"[bench] diag53_d12 {label} {prec}: {dt / nt:.2f} s/slice", file=sys.stderr, flush=True)
-            for prec in ("c64", "c64_bf16x3"):
-                if prec in parts and "c128" in parts:
+            for prec in parts:
+                if prec != "c128" and "c128" in parts:
                     r[prec]["partial_rel_l2_vs_c128"] = rel_l2(parts["c128"], parts[prec])
             if opts:
                 r["open_qubits"] = oq
