@@ -149,18 +149,19 @@ struct Server {
         // called with m held
         bool over = r->running == 0 && (r->finished >= r->n || r->status != TNS_OK || r->cancel);
         if (!over) return;
-        active.remove(r);
-        if (rr != active.end() && std::find(active.begin(), active.end(), *rr) == active.end())
-            rr = active.begin();
-        {
-            std::lock_guard<std::mutex> lk(r->m);
-            if (r->cancel && r->status == TNS_OK && r->finished < r->n) {
-                r->status = TNS_E_CANCELLED;
-                r->error = "request cancelled";
-            }
-            r->t_end = clk::now();
-            r->done = true;
+        // step the round-robin cursor off r before its node is erased
+        auto it = std::find(active.begin(), active.end(), r);
+        if (it == active.end()) return;   // already completed
+        if (rr == it) ++rr;
+        active.erase(it);
+        // notify under r->m: a waiter that sees done may free r at once
+        std::lock_guard<std::mutex> lk(r->m);
+        if (r->cancel && r->status == TNS_OK && r->finished < r->n) {
+            r->status = TNS_E_CANCELLED;
+            r->error = "request cancelled";
         }
+        r->t_end = clk::now();
+        r->done = true;
         r->cv.notify_all();
     }
 

@@ -257,7 +257,8 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
     const bool c64 = p.precision != TNS_C128;
     const int elem = c64 ? 8 : 16;
     const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget));
-    const bool timing = true;
+    // phase timing syncs the host on events: only when stats are asked for
+    const bool timing = st.profile;
 
     const int64_t opu = p.out_per_unit;   // amplitudes per bitstring (open qubits)
     double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * opu * 16, stream);
