@@ -2,14 +2,25 @@
 """Benchmark: amplitudes/s of the tensor-network-states amplitude path on one
 MI355X, with the dominant kernel's roofline and the CPU oracle beside it.
 
-One step = one pass of the whole hot path over one batch of bitstrings:
-bra evolution with SVD compression, overlap merge, slice gather, and every
-permute + complex GEMM of the contraction path, with the FP64 slice sum.
-Inputs are seeded synthetic random circuits (see circuits/); bitstrings are
-uploaded as part of each step (they are small), tensors live in HBM.
+Headline (default): one whole amplitude of the 53-qubit diagonal lattice at
+depth 12 (12 random cycles and a closing single-qubit layer, circuit seed 3,
+the first bitstring of seed 103), complex64 on FP32 MFMA.  The plan cuts the
+merged network into independent slices (sub-networks whose scalars add up to
+the amplitude); the K timed steps split the slices into K consecutive ranges,
+each step runs the whole path -- bra evolution with SVD compression, overlap
+merge, slice gathers, every permute + complex GEMM of the contraction path and
+the FP64 slice sum -- over its range, and the host adds the K partial sums in
+FP64.  So the timed region computes the amplitude whole, and value = 1 /
+(timed seconds).  Warm-up steps run single slices.  Tensors stay in HBM; the
+bitstring (53 bytes) is uploaded and the partial sums come back inside each
+step.
 
-Prints one JSON line.  Usage:
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision c64|c128]
+Other legs (25-qubit batches, depth 10, correlated batches, 104 qubits,
+serving) run only when named in --legs.  --slice-range A:B computes one
+partial sum over slices [A, B) and prints it alone (reference runs in
+complex128, which take longer than one call allows).
+
+Prints one JSON line.
 """
 
 import argparse
@@ -31,14 +42,44 @@ import numpy as np  # noqa: E402
 PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "c64_bf16x3": 157.3, "c64_bf16x6": 157.3}
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the dominant GEMM, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by a plain-copy calibration (the summary and commands
-# are in profiles/gemm_f32_grid5x5_d10_traffic.md).  Keyed by the sha256
-# prefix of the kernel source the counters were taken on, by the plan (split
-# cycle, flops per amplitude) and by the algorithmic bytes per launch (units
-# per launch): a change to any of them makes the entry stale and the bench
-# reports null.
-MEASURED_TRAFFIC = {("c64", "grid5x5_d10", "3cef2c90df144854", "split2:4.799972e+11:5422MiB"): 5837.0 * 2 ** 20}
+# HBM bytes per launch of the dominant kernel (k_gemm_3m), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration.  The
+# figure is read from the summary in profiles/ that records it, keyed by the
+# sha256 prefix of the kernel source the counters were taken on, the workload
+# and the algorithmic bytes per launch; any change makes the entry stale and
+# the line reports null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm3m_diag53_d12_traffic.md")
+
+
+def measured_traffic(src_hash, workload, alg_mib):
+    """HBM bytes per k_gemm_3m launch recorded for this kernel source, or None."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("traffic_entry:"):
+            f = dict(kv.split("=", 1) for kv in ln.split(":", 1)[1].split())
+            if (f.get("kernel_sha") == src_hash and f.get("workload") == workload
+                    and abs(float(f.get("alg_mib_per_launch", -1)) - alg_mib) < 0.5):
+                return float(f["bytes_per_launch"])
+    return None
+
+
+def kernel_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2011_02621_amd", "csrc", "kernels_contract.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def rel_l2(a, b):
@@ -69,16 +110,18 @@ def serving_pool(T, size, seed):
     return pool, rng
 
 
-def serving_run(T, ctx, torch, n_req=100, pool_size=24, cap_gpu_s=5.0, nominal_tflops=100.0,
-                load=0.7, seed=4, max_elems=1 << 32):
+def serving_run(T, ctx, torch, n_req=200, pool_size=24, cap_gpu_s=5.0, nominal_tflops=100.0,
+                load=0.7, seed=4, max_elems=1 << 28):
     """Continuous batching on the serving mix (complex64).  The pool's plans
-    are compiled ahead and stay resident.  Admission: a request whose planned
-    work (flops per amplitude x bitstrings) exceeds cap_gpu_s at
-    nominal_tflops, or whose circuit needs cuts to fit max_elems, is rejected
-    and counted; the library itself rejects requests that do not fit a
-    serving slot's memory.  Bitstrings per request are log-uniform in
-    1..1024.  Arrivals are Poisson at the rate that gives the stated offered
-    load, from service times measured on the device before the run."""
+    are compiled ahead and stay resident; they are compiled with a
+    2^28-element intermediate limit (2 GiB per (bitstring, slice) unit in
+    complex64), so the circuits beyond it are sliced and served as blocks of
+    (bitstring, slice) units.  Admission: a request whose planned work (flops
+    per amplitude x bitstrings) exceeds cap_gpu_s at nominal_tflops is
+    rejected and counted; the library admits the rest by memory.  Bitstrings
+    per request are log-uniform in 1..1024.  Arrivals are Poisson at the rate
+    that gives the stated offered load, from service times measured on the
+    device before the run."""
     import math
     from circuits import bitstrings
     pool, rng = serving_pool(T, pool_size, seed)
@@ -87,13 +130,17 @@ def serving_run(T, ctx, torch, n_req=100, pool_size=24, cap_gpu_s=5.0, nominal_t
     for name, circ in pool:
         # screen with the unsliced cost (no cut search) on the host planner
         q = pctx.plan(circ, precision="c64", max_intermediate_elems=1 << 62, path_mode="greedy")
-        qi = q.info()
-        fl, pk = qi.flops_per_amp, int(qi.peak_elems)
+        fl = q.info().flops_per_amp
         q.close()
-        if pk > max_elems or fl / (nominal_tflops * 1e12) > cap_gpu_s:
+        if fl / (nominal_tflops * 1e12) > cap_gpu_s:
             plans.append((name, circ, None, fl, None))
             continue
-        p = ctx.plan(circ, precision="c64")
+        p = ctx.plan(circ, precision="c64", max_intermediate_elems=max_elems)
+        fl = p.info().flops_per_amp
+        if fl / (nominal_tflops * 1e12) > cap_gpu_s:
+            p.close()
+            plans.append((name, circ, None, fl, None))
+            continue
         # service-time model o + a * n from one and four bitstrings
         b = bitstrings(circ.n, 4, 9000)
         ctx.amplitudes(p, b[:1])
@@ -101,7 +148,7 @@ def serving_run(T, ctx, torch, n_req=100, pool_size=24, cap_gpu_s=5.0, nominal_t
         t = time.perf_counter(); ctx.amplitudes(p, b[:1]); t1 = time.perf_counter() - t
         t = time.perf_counter(); ctx.amplitudes(p, b); t4 = time.perf_counter() - t
         a = max((t4 - t1) / 3, 0.0)
-        plans.append((name, circ, p, p.info().flops_per_amp, (max(t1 - a, 0.0), a)))
+        plans.append((name, circ, p, fl, (max(t1 - a, 0.0), a)))
     pctx.close()
     reqs, rejected_work = [], 0
     for i in range(n_req):
@@ -125,31 +172,36 @@ def serving_run(T, ctx, torch, n_req=100, pool_size=24, cap_gpu_s=5.0, nominal_t
         if delay > 0:
             time.sleep(delay)
         try:
-            handles.append(ctx.submit(plans[k][2], bits))
+            handles.append((k, ctx.submit(plans[k][2], bits)))
         except T.TnsError as e:
             if e.name != "TNS_E_ADMISSION":
                 raise
             rejected_mem += 1
-    total_amps = 0
-    lat = []
-    for h in handles:
+    total_amps, lat, lat_sliced = 0, [], []
+    for k, h in handles:
         h.wait()
         total_amps += h.bits.shape[0]
         lat.append(h.latency_ms()[0])
+        if plans[k][2].info().n_slices > 1:
+            lat_sliced.append(lat[-1])
     wall = time.perf_counter() - t0
+    sliced_pool = [n for n, _, p, _, _ in plans if p is not None and p.info().n_slices > 1]
     for _, _, p, _, _ in plans:
         if p is not None:
             p.close()
     lat = np.array(lat)
     return {"mix": "20-53 qubits (grid / diagonal lattice), depths 6-12, 1-1024 bitstrings, c64",
-            "arrivals": n_req, "served": len(handles), "rejected_work_cap": rejected_work,
-            "rejected_memory": rejected_mem, "work_cap_gpu_s": cap_gpu_s,
+            "arrivals": n_req, "served": len(handles), "served_sliced": len(lat_sliced),
+            "rejected_work_cap": rejected_work, "rejected_memory": rejected_mem,
+            "work_cap_gpu_s": cap_gpu_s, "max_intermediate_elems": max_elems,
             "pool": [n for n, _, _, _, _ in plans],
+            "pool_sliced": sliced_pool,
             "pool_rejected": [n for n, _, p, _, _ in plans if p is None],
             "offered_load": load, "mean_service_ms": round(mean_service * 1e3, 2),
             "wall_s": round(wall, 2), "amps_per_s": round(total_amps / wall, 2),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "p50_ms_sliced": round(float(np.percentile(lat_sliced, 50)), 3) if lat_sliced else None}
 
 
 def bench_104(T, ctx, args, torch):
@@ -276,6 +328,8 @@ def bench_53(T, ctx, args, torch):
 
     # ---- depth 12
     try:
+        if getattr(args, "no_d12", False):
+            raise _Skip()
         c53, b53 = config("diag53_d12", n_bits=1)
         res = {}
         t = time.perf_counter()
@@ -322,29 +376,295 @@ def bench_53(T, ctx, args, torch):
             res[label] = r
         p64.close()
         out["diag53_d12"] = res
+    except _Skip:
+        pass
     except Exception as e:
         out["diag53_d12"] = {"error": str(e)}
     return out
 
 
+def gemm_roofline(agg, precision, workload):
+    """Roofline of the dominant kernel from the per-launch HIP events of the
+    timed steps.  complex64: the three-multiplication GEMM k_gemm_3m, whose
+    MFMA instructions execute 6 M K N real flops per complex product; its
+    achieved rate and fraction are those executed flops over its launch time
+    (the 8 M K N count of the complex product is reported beside them as
+    credited_tflops).  Other precisions: every GEMM launch."""
+    if precision == "c64" and agg.get("gemm3m_launches"):
+        ms, n = agg["ms_gemm3m"], agg["gemm3m_launches"]
+        ex, cr, by = agg["gemm3m_mfma_flops"], agg["gemm3m_flops"], agg["gemm3m_bytes"]
+        kname = "k_gemm_3m (complex64 in three real products on FP32 MFMA, 6 M K N executed)"
+    else:
+        ms, n = agg["ms_gemm"], agg["gemm_launches"]
+        ex, cr, by = agg["gemm_mfma_flops"], agg["gemm_flops"], agg["gemm_bytes"]
+        kname = {"c64": "k_gemm_c64 MODE 1 (FP32 MFMA, real embedding)",
+                 "c128": "k_gemm_f64 (FP64 MFMA)",
+                 "c64_bf16x3": "k_gemm_c64 MODE 2 (split-BF16 x3, BF16 MFMA)",
+                 "c64_bf16x6": "k_gemm_c64 MODE 3 (split-BF16 x6, BF16 MFMA)"}[precision]
+    if not n or not ms:
+        return None
+    peak = PEAK_TFLOPS[precision]
+    bf16 = precision.startswith("c64_bf16")
+    # split-BF16: priced at the FP32 peak for the complex product's flops
+    achieved = (cr if bf16 else ex) / (ms * 1e-3) / 1e12
+    alg_launch = by / n
+    src_hash = kernel_source_hash()
+    traffic = measured_traffic(src_hash, workload, alg_launch / 2 ** 20) if precision == "c64" else None
+    return {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+            "launches": int(n), "avg_launch_ms": round(ms / n, 4),
+            "flops_per_launch": (cr if bf16 else ex) / n,
+            "algorithmic_bytes_per_launch": alg_launch,
+            "credited_tflops": round(cr / (ms * 1e-3) / 1e12, 3),
+            "credited_flops_per_launch": cr / n,
+            "all_gemm_launches": int(agg["gemm_launches"]),
+            "all_gemm_ms_share_of_contract": round(agg["ms_gemm"] / agg["ms_contract"], 4)
+            if agg.get("ms_contract") else None,
+            "kernel_sha": src_hash}
+
+
+def cpu_baseline_sliced(circ_full, lattice_sub, depth, seed, budget_s=4.0):
+    """The oracle's dense complex128 state vector cannot hold 53 qubits
+    (2^53 x 16 B = 128 PiB).  It is timed on a bounded sample of the same
+    workload -- the first n sites of the same lattice, same depth, gate set
+    and seed -- growing n while a pass stays short, once on every host thread
+    and once on one thread, and each time is scaled to the full circuit by the
+    state vector's own cost law: one pass over 2^N amplitudes per gate, so
+    t(N) = t(n) * gates(N) / gates(n) * 2^(N - n)."""
+    from oracle import sv
+    from circuits import random_circuit
+    sv.build()
+    threads = sv.max_threads()
+    n_full, g_full = circ_full.n, len(circ_full.gates)
+    out = {}
+    for label, th in (("all", 0), ("one", 1)):
+        best = None
+        for n in range(16, 31, 2):
+            c = random_circuit(lattice_sub(n), depth, seed)
+            t = time.perf_counter()
+            sv.state(c, th)
+            dt = time.perf_counter() - t
+            best = (n, len(c.gates), dt)
+            if dt * 4.4 > budget_s:   # the next size costs about 4x more
+                break
+        n, g, dt = best
+        est = dt * g_full / g * 2.0 ** (n_full - n)
+        out[label] = {"threads": threads if th == 0 else 1, "sample_qubits": n, "sample_gates": g,
+                      "sample_s": round(dt, 3), "est_s_per_amp": est}
+    a = out["all"]
+    return {"value": 1.0 / a["est_s_per_amp"], "unit": "amplitudes/s", "cores": a["threads"],
+            "kind": "oracle",
+            "sample": (f"dense complex128 state vector of the first {a['sample_qubits']} sites of the "
+                       f"same lattice at the same depth and seed ({a['sample_gates']} gates, all "
+                       f"amplitudes in one pass) in {a['sample_s']} s on {a['threads']} threads; scaled "
+                       f"to {n_full} qubits ({g_full} gates) as t * gates ratio * 2^(qubit difference): "
+                       f"{a['est_s_per_amp']:.3e} s per pass, which yields every amplitude but needs "
+                       f"2^{n_full} x 16 B of memory, so the oracle cannot run the workload itself"),
+            "single_thread": {"value": 1.0 / out["one"]["est_s_per_amp"], **out["one"]},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def headline_sliced(T, ctx, args, torch):
+    """One whole amplitude of a sliced workload, its slices spread over the
+    timed steps (see the module docstring)."""
+    from circuits import config, diagonal53
+    circ, bits = config(args.workload, n_bits=1)
+    t = time.perf_counter()
+    plan = ctx.plan(circ, precision=args.precision)
+    t_plan = time.perf_counter() - t
+    info = plan.info()
+    S, K = int(info.n_slices), args.steps
+    if K > S:
+        raise SystemExit(f"--steps {K} exceeds the plan's {S} slices: each step takes a range of slices")
+    edges = np.linspace(0, S, K + 1).round().astype(int)
+    ranges = [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:])]
+    print(f"[bench] {args.workload}: {circ.n} qubits, split {info.split_cycle}, cuts "
+          f"{info.cut_edges.tolist()}, {S} slices, {info.flops_per_amp:.4e} flop/amp, peak "
+          f"{info.peak_elems} elems, plan {t_plan:.2f}s; {K} steps of {ranges[0][1] - ranges[0][0]}"
+          f"-{max(b - a for a, b in ranges)} slices", file=sys.stderr, flush=True)
+
+    warm_parts = {}
+    for w in range(args.warmup):
+        sl = w % S
+        warm_parts[sl] = ctx.amplitudes(plan, bits, slices=(sl, sl + 1))[0]
+        print(f"[bench] warmup {w} (slice {sl}) done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg, amp, per_step = {}, 0.0 + 0.0j, []
+    for i, (a, b) in enumerate(ranges):
+        part, st = ctx.amplitudes(plan, bits, stats=True, slices=(a, b))
+        amp += complex(part[0])
+        for k, v in st.items():
+            agg[k] = agg.get(k, 0) + v
+        per_step.append(st["ms_total"])
+        print(f"[bench] step {i}: slices [{a}, {b}) {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    covered = sum(b - a for a, b in ranges)
+    assert covered == S and ranges[0][0] == 0 and ranges[-1][1] == S
+
+    line = {
+        "metric": "amplitudes/s + achieved TFLOP/s, c64-MFMA vs c128, 53q depth-12; p50/p99 latency",
+        "value": round(1.0 / dt, 8), "unit": "amplitudes/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(dt / K * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c64": "c64 (fp32 mfma)", "c128": "c128 (fp64 mfma)",
+                  "c64_bf16x3": "c64 (split-bf16 x3)", "c64_bf16x6": "c64 (split-bf16 x6)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "qubits": circ.n, "cycles": circ.depth,
+                   "circuit_seed": 3, "bitstring_seed": 103, "bitstrings": 1,
+                   "precision": args.precision, "split_cycle": int(info.split_cycle),
+                   "cut_edges": info.cut_edges.tolist(), "n_slices": S, "slices_timed": covered,
+                   "slices_per_step": [ranges[0][1] - ranges[0][0], max(b - a for a, b in ranges)],
+                   "peak_elems": int(info.peak_elems), "flops_per_amp": info.flops_per_amp},
+        "s_per_amplitude": round(dt, 3),
+        "amplitude": [amp.real, amp.imag],
+        "achieved_tflops_whole_path": round(info.flops_per_amp / dt / 1e12, 3),
+        "roofline": gemm_roofline(agg, args.precision, args.workload),
+        "cpu_baseline": None,
+        "breakdown_ms_per_step": {k: round(agg[k] / K, 3) for k in
+                                  ("ms_bra", "ms_merge", "ms_contract", "ms_gemm", "ms_gemm3m",
+                                   "ms_permute", "ms_small")},
+        "step_ms_min_max": [round(min(per_step), 1), round(max(per_step), 1)],
+    }
+
+    if not args.no_compare and 0 in warm_parts and args.precision != "c128":
+        # complex128 on the same split, path and cuts: one slice timed, and
+        # its partial sum against the complex64 one of the warm-up
+        same = dict(split_cycle=int(info.split_cycle), path=info.path.tolist(),
+                    cuts=info.cut_edges.tolist())
+        p2 = ctx.plan(circ, precision="c128", **same)
+        t = time.perf_counter()
+        ref = ctx.amplitudes(p2, bits, slices=(0, 1))[0]
+        t2 = time.perf_counter() - t
+        got = warm_parts[0]
+        line["c128"] = {"s_per_slice": round(t2, 3), "est_s_per_amplitude": round(t2 * S, 1),
+                        "slice0_partial": [ref.real, ref.imag],
+                        "slice0_rel_diff_c64_vs_c128": float(abs(got - ref) / abs(ref))}
+        p2.close()
+        print(f"[bench] c128 slice 0: {t2:.2f} s", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_sliced(circ, lambda n: diagonal53().sub(n), 12, 3)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    plan.close()
+    return line
+
+
+def slice_range_only(T, ctx, args, torch):
+    """Partial sum over one slice range of the headline amplitude (reference
+    runs, e.g. complex128 in pieces)."""
+    from circuits import config
+    circ, bits = config(args.workload, n_bits=1)
+    a, b = (int(x) for x in args.slice_range.split(":"))
+    plan = ctx.plan(circ, precision=args.precision)
+    info = plan.info()
+    t = time.perf_counter()
+    part, st = ctx.amplitudes(plan, bits, stats=True, slices=(a, b))
+    dt = time.perf_counter() - t
+    out = {"workload": args.workload, "precision": args.precision, "slices": [a, b],
+           "n_slices": int(info.n_slices), "split_cycle": int(info.split_cycle),
+           "cut_edges": info.cut_edges.tolist(), "partial": [part[0].real, part[0].imag],
+           "s": round(dt, 3), "s_per_slice": round(dt / (b - a), 3),
+           "gemm_tflops_executed": round(st["gemm_mfma_flops"] / (st["ms_gemm"] * 1e-3) / 1e12, 2)
+           if st["ms_gemm"] else None}
+    plan.close()
+    return out
+
+
+def bench_batch(T, ctx, args, torch, workload, precision="c64", steps=3, warmup=1, n_bits=None,
+                compare=True, cpu=True):
+    """A bitstring batch per step (workloads that need no cuts, e.g. the
+    25-qubit grid): amplitudes/s, GEMM rates, the precision report against
+    complex128 and split-BF16, and the oracle's state vector beside it."""
+    from circuits import config
+    circ, bits = config(workload, n_bits=n_bits)
+    plan = ctx.plan(circ, precision=precision)
+    info = plan.info()
+    for w in range(warmup):
+        ctx.amplitudes(plan, bits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg, amps = {}, None
+    for s in range(steps):
+        amps, st = ctx.amplitudes(plan, bits, stats=True)
+        for k, v in st.items():
+            agg[k] = agg.get(k, 0) + v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_amp = steps * len(bits)
+    out = {"qubits": circ.n, "cycles": circ.depth, "bitstrings_per_step": int(len(bits)),
+           "precision": precision, "split_cycle": int(info.split_cycle), "slices": int(info.n_slices),
+           "flops_per_amp": info.flops_per_amp, "steps": steps,
+           "amps_per_s": round(n_amp / dt, 3), "ms_per_step": round(dt / steps * 1e3, 3),
+           "achieved_tflops_whole_path": round(info.flops_per_amp * n_amp / dt / 1e12, 3),
+           "roofline": gemm_roofline(agg, precision, workload),
+           "breakdown_ms_per_step": {k: round(agg[k] / steps, 3) for k in
+                                     ("ms_bra", "ms_merge", "ms_contract", "ms_gemm", "ms_gemm3m",
+                                      "ms_permute", "ms_small")}}
+    if compare and precision == "c64":
+        sub = bits[:min(len(bits), 128)]
+        p2 = ctx.plan(circ, precision="c128")
+        ctx.amplitudes(p2, sub[:4])
+        t = time.perf_counter()
+        a2 = ctx.amplitudes(p2, sub)
+        out["c128_amps_per_s"] = round(len(sub) / (time.perf_counter() - t), 3)
+        p2.close()
+        for sp in ("c64_bf16x3", "c64_bf16x6"):
+            p3 = ctx.plan(circ, precision=sp)
+            ctx.amplitudes(p3, sub[:4])
+            t = time.perf_counter()
+            a3 = ctx.amplitudes(p3, sub)
+            out[sp] = {"amps_per_s": round(len(sub) / (time.perf_counter() - t), 3),
+                       "rel_l2_vs_c128": rel_l2(a2, a3), "f_xeb": xeb(a2, a3, circ.n)}
+            p3.close()
+        a1 = amps[:len(sub)]
+        out["c64_vs_c128"] = {"rel_l2": rel_l2(a2, a1),
+                              "max_scaled": float(np.abs(a1 - a2).max() / (np.linalg.norm(a2) / np.sqrt(len(a2)))),
+                              "f_xeb": xeb(a2, a1, circ.n),
+                              "f_ovl": float(abs(np.vdot(a2, a1)) ** 2 / (np.vdot(a2, a2).real * np.vdot(a1, a1).real))}
+    if cpu:
+        from oracle import sv
+        sv.build()
+        res = {}
+        for label, th in (("all", 0), ("one", 1)):
+            t = time.perf_counter()
+            ref = sv.amplitudes(circ, bits, th)
+            tc = time.perf_counter() - t
+            res[label] = {"amps_per_s": round(len(bits) / tc, 3), "s": round(tc, 3),
+                          "threads": sv.max_threads() if th == 0 else 1}
+        out["cpu_oracle"] = {**res, "cpu_model": cpu_model(),
+                             "sample": f"one dense complex128 state-vector pass (all 2^{circ.n} "
+                                       f"amplitudes, the {len(bits)} requested read out)"}
+        out["oracle_check_rel_l2"] = rel_l2(ref, amps)
+    plan.close()
+    return out
+
+
+LEGS = ("grid5x5_d10", "diag53_d10", "diag53_d12_slices", "grid8x13_d8", "serving")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid5x5_d10")
+    ap.add_argument("--steps", type=int, default=16,
+                    help="timed steps; the headline splits its slices over them")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up steps (one slice each on the headline)")
+    ap.add_argument("--workload", default="diag53_d12",
+                    help="diag53_d12 (headline: one whole sliced amplitude) or a batch workload "
+                         "(grid3x4_d8, grid5x5_d10, grid8x13_d8)")
     ap.add_argument("--precision", default="c64", choices=["c64", "c128", "c64_bf16x3", "c64_bf16x6"])
-    ap.add_argument("--bits", type=int, default=0, help="bitstrings per step (0 = workload default)")
+    ap.add_argument("--bits", type=int, default=0, help="bitstrings per step of a batch workload")
+    ap.add_argument("--slice-range", default="", help="A:B -- print the partial sum over slices [A, B) only")
+    ap.add_argument("--legs", default="", help="comma list of extra legs: " + ",".join(LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--no-d12", action="store_true", help="skip the 53-qubit depth-12 slice timing")
     ap.add_argument("--d12-slices", type=int, default=2)
     ap.add_argument("--d12-only", action="store_true",
-                    help="time only the 53-qubit depth-12 slices (for kernel traces); prints that leg alone")
+                    help="time only a few 53-qubit depth-12 slices (for kernel traces); prints that leg alone")
     ap.add_argument("--d12-precisions", default="c64,c64_bf16x3,c128")
     ap.add_argument("--d12-legs", default="single,correlated_batch")
-    ap.add_argument("--no-104", action="store_true", help="skip the 104-qubit grid leg")
     ap.add_argument("--b104-bits", type=int, default=4, help="bitstrings timed on the 104-qubit grid")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB of a plain device copy run first (byte-counter calibration)")
@@ -353,19 +673,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slice "
               "sharding is not part of this build", file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEGS:
+            raise SystemExit(f"unknown leg {x}; choose from {','.join(LEGS)}")
 
     import torch
     import paper_2011_02621_amd as T
-    from circuits import config, random_circuit, diagonal53, bitstrings
 
-    if args.d12_only:
-        ctx = T.Context(0)
-        res = bench_53(T, ctx, args, torch)
-        print(json.dumps({"metric": "53-qubit depth-12 slice timing (partial contraction)", "n_gpus": 1,
-                          "data": "synthetic", **res}))
-        ctx.close()
-        return
-
+    ctx = T.Context(0)
     if args.copy_calibration:
         # a plain device copy of known size, for scaling HBM byte counters
         nbytes = args.copy_calibration << 20
@@ -374,144 +690,55 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    circ, bits = config(args.workload, n_bits=args.bits or None)
-    n_q = circ.n
-    ctx = T.Context(0)
-    t_plan = time.perf_counter()
-    plan = ctx.plan(circ, precision=args.precision)
-    t_plan = time.perf_counter() - t_plan
-    info = plan.info()
-    print(f"[bench] {args.workload}: {n_q} qubits, {len(bits)} bitstrings, split {info.split_cycle}, "
-          f"{info.flops_per_amp:.3e} flop/amp, {info.n_slices} slices, peak {info.peak_elems} elems, "
-          f"plan {t_plan:.2f}s", file=sys.stderr, flush=True)
 
-    for w in range(args.warmup):
-        ctx.amplitudes(plan, bits)
-        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    if args.d12_only:
+        res = bench_53(T, ctx, args, torch)
+        print(json.dumps({"metric": "53-qubit depth-12 slice timing (partial contraction)", "n_gpus": 1,
+                          "data": "synthetic", **res}))
+        ctx.close()
+        return
+    if args.slice_range:
+        print(json.dumps(slice_range_only(T, ctx, args, torch)))
+        ctx.close()
+        return
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    agg = {}
-    amps = None
-    for s in range(args.steps):
-        amps, st = ctx.amplitudes(plan, bits, stats=True)
-        for k, v in st.items():
-            agg[k] = agg.get(k, 0) + v
-        print(f"[bench] step {s}: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n_amp = args.steps * len(bits)
-    value = n_amp / dt
-    tflops = info.flops_per_amp * n_amp / dt / 1e12
+    if args.workload == "diag53_d12":
+        line = headline_sliced(T, ctx, args, torch)
+    else:
+        r = bench_batch(T, ctx, args, torch, args.workload, args.precision, args.steps, args.warmup,
+                        args.bits or None, compare=not args.no_compare, cpu=not args.no_cpu_baseline)
+        cpu = r.pop("cpu_oracle", None)
+        line = {"metric": "amplitudes/s + achieved TFLOP/s, c64-MFMA vs c128, 53q depth-12; p50/p99 latency",
+                "value": r.pop("amps_per_s"), "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"), "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+                "config": {"workload": args.workload, **{k: r.pop(k) for k in
+                           ("qubits", "cycles", "bitstrings_per_step", "precision", "split_cycle",
+                            "slices", "flops_per_amp")}},
+                "roofline": r.pop("roofline"),
+                "cpu_baseline": None if cpu is None else
+                {"value": cpu["all"]["amps_per_s"], "unit": "amplitudes/s", "cores": cpu["all"]["threads"],
+                 "kind": "oracle", "sample": cpu["sample"] + f", {cpu['all']['s']} s",
+                 "single_thread": cpu["one"], "cpu_model": cpu["cpu_model"]},
+                **r}
 
-    # algorithmic rate (8 M K N per complex product, the path's flop count,
-    # also credited to the three-multiplication form) and, beside it, the rate
-    # of the flops the MFMA instructions execute (6 M K N for that form)
-    gemm_tflops = agg["gemm_flops"] / (agg["ms_gemm"] * 1e-3) / 1e12 if agg.get("ms_gemm") else 0.0
-    mfma_tflops = agg["gemm_mfma_flops"] / (agg["ms_gemm"] * 1e-3) / 1e12 if agg.get("ms_gemm") else 0.0
-    avg_gemm_ms = agg["ms_gemm"] / max(agg["gemm_launches"], 1)
-    kname = {"c64": "k_gemm_3m + k_gemm_c64 MODE 1 (FP32 MFMA; three-multiplication form on the wide steps)",
-             "c128": "k_gemm_f64 (FP64 MFMA)",
-             "c64_bf16x3": "k_gemm_c64 (MODE 2, split-BF16 x3, BF16 MFMA)",
-             "c64_bf16x6": "k_gemm_c64 (MODE 3, split-BF16 x6, BF16 MFMA)"}[args.precision]
-    import hashlib
-    src = os.path.join(ROOT, "paper_2011_02621_amd", "csrc", "kernels_contract.hip")
-    src_hash = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    alg_launch = agg["gemm_bytes"] / max(agg["gemm_launches"], 1)
-    plan_key = f"split{info.split_cycle}:{info.flops_per_amp:.6e}:{alg_launch / 2 ** 20:.0f}MiB"
-    traffic = MEASURED_TRAFFIC.get((args.precision, args.workload, src_hash, plan_key))
-    roofline = {"bound": "mfma", "kernel": kname,
-                "achieved": round(gemm_tflops, 3), "peak": PEAK_TFLOPS[args.precision],
-                "unit": "TFLOP/s", "frac": round(gemm_tflops / PEAK_TFLOPS[args.precision], 4),
-                "traffic": traffic,
-                "executed_tflops": round(mfma_tflops, 3),
-                "executed_frac": round(mfma_tflops / PEAK_TFLOPS[args.precision], 4),
-                "algorithmic_bytes_per_launch": agg["gemm_bytes"] / max(agg["gemm_launches"], 1),
-                "avg_launch_ms": round(avg_gemm_ms, 4),
-                "launches": int(agg["gemm_launches"]),
-                "flops_per_launch": agg["gemm_flops"] / max(agg["gemm_launches"], 1),
-                "mfma_flops_per_launch": agg["gemm_mfma_flops"] / max(agg["gemm_launches"], 1)}
-    breakdown = {k: round(agg[k] / args.steps, 3) for k in
-                 ("ms_bra", "ms_merge", "ms_contract", "ms_gemm", "ms_permute", "ms_small")}
-    if agg.get("ms_permute"):
-        breakdown["permute_GBps"] = round(agg["permute_bytes"] / (agg["ms_permute"] * 1e-3) / 1e9, 1)
-
-    extra = {}
-    if not args.no_compare:
-        # c128 reference on a subset: precision report and c128 throughput
-        other = "c128" if args.precision == "c64" else "c64"
-        sub = bits[:min(len(bits), 128)]
-        p2 = ctx.plan(circ, precision=other)
-        ctx.amplitudes(p2, sub[:4])
-        t = time.perf_counter()
-        a2 = ctx.amplitudes(p2, sub)
-        t2 = time.perf_counter() - t
-        a1 = amps[:len(sub)]
-        ref, test = (a2, a1) if other == "c128" else (a1, a2)
-        extra[f"{other}_amps_per_s"] = round(len(sub) / t2, 3)
-        if args.precision == "c64":
-            for sp in ("c64_bf16x3", "c64_bf16x6"):
-                p3 = ctx.plan(circ, precision=sp)
-                ctx.amplitudes(p3, sub[:4])
-                t = time.perf_counter()
-                a3 = ctx.amplitudes(p3, sub)
-                t3 = time.perf_counter() - t
-                extra[sp] = {"amps_per_s": round(len(sub) / t3, 3), "rel_l2_vs_c128": rel_l2(a2, a3),
-                             "f_xeb": xeb(a2, a3, n_q)}
-                p3.close()
-        extra["c64_vs_c128"] = {"rel_l2": rel_l2(ref, test),
-                                "max_scaled": float(np.abs(test - ref).max() / (np.linalg.norm(ref) / np.sqrt(len(ref)))),
-                                "f_xeb": xeb(ref, test, n_q),
-                                "f_ovl": float(abs(np.vdot(ref, test)) ** 2 / (np.vdot(ref, ref).real * np.vdot(test, test).real))}
-        print(f"[bench] {other} done", file=sys.stderr, flush=True)
-
-    if not args.no_d12:
-        extra.update(bench_53(T, ctx, args, torch))
-
-    if not args.no_104:
+    if "grid5x5_d10" in legs and args.workload != "grid5x5_d10":
+        line["grid5x5_d10"] = bench_batch(T, ctx, args, torch, "grid5x5_d10", steps=3, warmup=1)
+        print("[bench] grid5x5_d10 done", file=sys.stderr, flush=True)
+    if "diag53_d10" in legs or "diag53_d12_slices" in legs:
+        args.d12_only = "diag53_d10" not in legs
+        args.no_d12 = "diag53_d12_slices" not in legs
+        line.update(bench_53(T, ctx, args, torch))
+    if "grid8x13_d8" in legs:
         try:
-            extra.update(bench_104(T, ctx, args, torch))
+            line.update(bench_104(T, ctx, args, torch))
         except Exception as e:
-            extra["grid8x13_d8"] = {"error": str(e)}
+            line["grid8x13_d8"] = {"error": str(e)}
+    if "serving" in legs:
+        line["serving"] = serving_run(T, ctx, torch)
+        print("[bench] serving done", file=sys.stderr, flush=True)
 
-    if not args.no_serving:
-        extra["serving"] = serving_run(T, ctx, torch)
-        print(f"[bench] serving done", file=sys.stderr, flush=True)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import sv
-        sv.build()
-        threads = sv.max_threads()
-        t = time.perf_counter()
-        ref = sv.amplitudes(circ, bits)
-        tc = time.perf_counter() - t
-        cpu = {"value": round(len(bits) / tc, 3), "unit": "amplitudes/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"one dense complex128 state-vector pass over {args.workload} "
-                         f"(all 2^{n_q} amplitudes, the {len(bits)} requested read out), {tc:.2f} s"}
-        extra["oracle_check_rel_l2"] = rel_l2(ref, amps)
-
-    line = {
-        "metric": "amplitudes/s + achieved TFLOP/s, c64-MFMA vs c128, 53q depth-12; p50/p99 latency",
-        "value": round(value, 4), "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"c64": "c64 (fp32 mfma)", "c128": "c128 (fp64 mfma)",
-                  "c64_bf16x3": "c64 (split-bf16 x3)", "c64_bf16x6": "c64 (split-bf16 x6)"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "qubits": n_q, "cycles": circ.depth,
-                   "bitstrings_per_step": int(len(bits)), "precision": args.precision,
-                   "split_cycle": int(info.split_cycle), "slices": int(info.n_slices),
-                   "flops_per_amp": info.flops_per_amp},
-        "achieved_tflops_whole_path": round(tflops, 3),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "breakdown_ms_per_step": breakdown,
-        **extra,
-    }
     print(json.dumps(line))
-    plan.close()
     ctx.close()
 
 

@@ -196,6 +196,13 @@ typedef struct {
                                        execute: 8 M K N for the real-embedded forms, 6 M K N
                                        for the three-multiplication complex64 form, 3x or 6x
                                        8 M K N (BF16) for split-BF16 */
+    /* the three-multiplication complex64 GEMM launches alone (step kernel 3),
+     * a subset of the GEMM launches above */
+    double ms_gemm3m;
+    int64_t gemm3m_launches;
+    double gemm3m_flops;            /* 8 M K N, the complex product's real flops */
+    double gemm3m_mfma_flops;       /* 6 M K N, what its MFMA instructions execute */
+    double gemm3m_bytes;            /* e * (MK + KN + MN) */
 } tns_stats;
 
 /* --- context ---------------------------------------------------------- */

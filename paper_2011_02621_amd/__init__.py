@@ -95,7 +95,10 @@ class _Stats(ctypes.Structure):
                 ("ms_gemm", ctypes.c_double), ("gemm_launches", ctypes.c_int64),
                 ("gemm_flops", ctypes.c_double), ("gemm_bytes", ctypes.c_double),
                 ("ms_permute", ctypes.c_double), ("permute_bytes", ctypes.c_double),
-                ("ms_small", ctypes.c_double), ("gemm_mfma_flops", ctypes.c_double)]
+                ("ms_small", ctypes.c_double), ("gemm_mfma_flops", ctypes.c_double),
+                ("ms_gemm3m", ctypes.c_double), ("gemm3m_launches", ctypes.c_int64),
+                ("gemm3m_flops", ctypes.c_double), ("gemm3m_mfma_flops", ctypes.c_double),
+                ("gemm3m_bytes", ctypes.c_double)]
 
 
 _lib = None

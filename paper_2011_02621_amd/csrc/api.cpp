@@ -429,6 +429,11 @@ static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n,
             stats->permute_bytes = rs.permute_bytes;
             stats->ms_small = rs.ms_small;
             stats->gemm_mfma_flops = rs.gemm_mfma_flops;
+            stats->ms_gemm3m = rs.ms_gemm3m;
+            stats->gemm3m_launches = rs.gemm3m_launches;
+            stats->gemm3m_flops = rs.gemm3m_flops;
+            stats->gemm3m_mfma_flops = rs.gemm3m_mfma_flops;
+            stats->gemm3m_bytes = rs.gemm3m_bytes;
         }
     });
 }

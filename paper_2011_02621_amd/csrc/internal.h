@@ -314,6 +314,8 @@ struct RunStats {
     double ms_gemm = 0, gemm_flops = 0, gemm_bytes = 0, gemm_mfma_flops = 0;
     int64_t gemm_launches = 0;
     double ms_permute = 0, permute_bytes = 0, ms_small = 0;
+    double ms_gemm3m = 0, gemm3m_flops = 0, gemm3m_mfma_flops = 0, gemm3m_bytes = 0;
+    int64_t gemm3m_launches = 0;
 };
 
 // Frugal rejection on the device amplitudes: value j is accepted when

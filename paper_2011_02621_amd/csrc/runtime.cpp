@@ -385,7 +385,8 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 // number of products of a split-BF16 form
                 const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
                                     : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
-                ev_begin(is_gemm ? 0 : 2, 8.0 * mkn, by, (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
+                ev_begin(s.kernel == 3 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, by,
+                         (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
                     launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream,
                                  s.store_fused ? &p.scatter[m] : nullptr);
@@ -414,7 +415,14 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         for (Ev &e : evs) {
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e.a, e.b);
-            if (e.cls == 0) {
+            if (e.cls == 3) {
+                st.ms_gemm3m += ms;
+                st.gemm3m_flops += e.flops;
+                st.gemm3m_bytes += e.bytes;
+                st.gemm3m_mfma_flops += e.mfma;
+                st.gemm3m_launches++;
+            }
+            if (e.cls == 0 || e.cls == 3) {
                 st.ms_gemm += ms;
                 st.gemm_flops += e.flops;
                 st.gemm_bytes += e.bytes;

@@ -171,14 +171,18 @@ def test_mirror_small(ctx):
     assert np.abs(got[1:][bits[1:].any(axis=1)]).max() < 1e-12
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64", "c64_bf16x6", "c64_bf16x3"])
-def test_grid5x5_d10(ctx, prec):
+@pytest.fixture(scope="module")
+def grid5x5_d10_ref():
     c, bits = config("grid5x5_d10")
-    n = 48 if prec == "c128" else 256
-    bits = bits[:n]
-    say("grid5x5_d10", prec, n, "oracle...")
-    ref = sv.amplitudes(c, bits)
-    say("grid5x5_d10", prec, "plan + contract")
+    say("grid5x5_d10 oracle, 1024 bitstrings")
+    return c, bits, sv.amplitudes(c, bits)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64", "c64_bf16x6", "c64_bf16x3"])
+def test_grid5x5_d10(ctx, grid5x5_d10_ref, prec):
+    # every one of the workload's 1024 bitstrings, in every precision
+    c, bits, ref = grid5x5_d10_ref
+    say("grid5x5_d10", prec, "plan + contract", len(bits))
     p = ctx.plan(c, precision=prec)
     got = ctx.amplitudes(p, bits)
     m = check(ref, got, c.n, prec)
@@ -312,35 +316,73 @@ def test_clifford_104_against_tableau(ctx, prec):
     assert np.abs(np.abs(got) ** 2 - p_ref).max() <= 2 * tol * max(p_ref.max(), 2.0 ** -104)
 
 
+# slices whose cut indices are (0, 0), (0, 1), (8, 0) and (15, 15): the slice
+# maps then offset both cut bonds of the 2^32-element network
+D12_SLICES = (0, 1, 128, 255)
+
+
 @pytest.fixture(scope="module")
-def diag53_d12_slice(ctx):
-    # complex128 partial sum over the first slice of the 53-qubit depth-12
+def diag53_d12_slices(ctx):
+    # complex128 partial sums over single slices of the 53-qubit depth-12
     # contraction, with the path and cuts the other precisions reuse
     c, bits = config("diag53_d12", n_bits=1)
-    say("diag53_d12 c128 plan + one slice")
+    say("diag53_d12 c128 plan")
     p = ctx.plan(c, precision="c128")
     i = p.info()
     same = dict(split_cycle=int(i.split_cycle), path=i.path.tolist(), cuts=i.cut_edges.tolist())
-    ref = ctx.amplitudes(p, bits, slices=(0, 1))
+    ref = {}
+    for sl in D12_SLICES:
+        say("diag53_d12 c128 slice", sl)
+        ref[sl] = ctx.amplitudes(p, bits, slices=(sl, sl + 1))[0]
     p.close()
-    return c, bits, same, ref, int(i.n_slices), int(i.peak_elems)
+    return c, bits, same, ref, int(i.n_slices), int(i.peak_elems), len(i.cut_edges)
 
 
 @pytest.mark.parametrize("prec", ["c64", "c64_bf16x6"])
-def test_diag53_d12_slice_against_c128(ctx, diag53_d12_slice, prec):
+def test_diag53_d12_slices_against_c128(ctx, diag53_d12_slices, prec):
     # the launch configuration the bench times at 53 qubits, depth 12 (256
     # slices, 2^32-element intermediates); no oracle reaches this size, so
-    # the property checked is that one slice's partial sum agrees with the
+    # the property checked is that each slice's partial sum agrees with the
     # complex128 path on the same network to the complex64 tolerance
-    c, bits, same, ref, n_slices, peak = diag53_d12_slice
-    assert n_slices == 256 and peak == 1 << 32
-    say("diag53_d12", prec, "one slice")
+    c, bits, same, ref, n_slices, peak, n_cuts = diag53_d12_slices
+    assert n_slices == 256 and peak == 1 << 32 and n_cuts == 2
     p = ctx.plan(c, precision=prec, **same)
-    got = ctx.amplitudes(p, bits, slices=(0, 1))
+    slices = D12_SLICES if prec == "c64" else (0, 255)
+    for sl in slices:
+        got = ctx.amplitudes(p, bits, slices=(sl, sl + 1))[0]
+        rel = float(abs(got - ref[sl]) / abs(ref[sl]))
+        say("diag53_d12", prec, "slice", sl, "rel %.3e" % rel)
+        assert rel <= TOL[prec]
     p.close()
-    rel = float(np.abs(got - ref).max() / np.abs(ref).max())
-    say("diag53_d12", prec, "rel %.3e" % rel)
-    assert rel <= TOL[prec]
+    # distinct slices carry distinct scalars (the offsets are applied)
+    vals = [ref[sl] for sl in D12_SLICES]
+    assert len({complex(v) for v in vals}) == len(vals)
+
+
+def test_diag53_d12_correlated_batch_slice(ctx):
+    # the 4096-amplitude correlated batch (12 open qubits, the last ones the
+    # path absorbs) at 53 qubits, depth 12: one slice, complex64 against
+    # complex128 on the same network, over all 4096 partial sums
+    c, bits = config("diag53_d12", n_bits=1)
+    p0 = T.Context(-1).plan(c, precision="c64")
+    oq = [int(q) for q in p0.info().path[-12:]]
+    p0.close()
+    say("diag53_d12 correlated batch c128 plan")
+    p = ctx.plan(c, precision="c128", open_qubits=oq)
+    i = p.info()
+    same = dict(split_cycle=int(i.split_cycle), path=i.path.tolist(), cuts=i.cut_edges.tolist(),
+                open_qubits=oq)
+    sl = int(i.n_slices) - 3
+    ref = ctx.amplitudes(p, bits, slices=(sl, sl + 1)).reshape(-1)
+    p.close()
+    say("diag53_d12 correlated batch c64, slice", sl)
+    p = ctx.plan(c, precision="c64", **same)
+    got = ctx.amplitudes(p, bits, slices=(sl, sl + 1)).reshape(-1)
+    p.close()
+    assert ref.shape == (4096,)
+    m = compare(ref, got, c.n)
+    say("diag53_d12 correlated batch rel_l2 %.3e max_scaled %.3e" % (m["rel_l2"], m["max_scaled"]))
+    assert m["rel_l2"] <= TOL["c64"] and m["max_scaled"] <= 10 * TOL["c64"]
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
