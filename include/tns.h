@@ -220,6 +220,9 @@ tns_status tns_set_allocator(tns_ctx *ctx,
                              void (*free_)(void *ptr, void *stream, void *user),
                              void *user);
 
+/* Stops the serving workers and frees the context.  Plans created on a
+ * device context hold its device memory: tns_finalize fails with
+ * TNS_E_INVALID_ARG while any of them is alive (destroy them first). */
 tns_status tns_finalize(tns_ctx *ctx);
 
 /* --- plans ------------------------------------------------------------ */
@@ -284,14 +287,30 @@ tns_status tns_sample_frugal(tns_ctx *ctx, const tns_plan *plan, int64_t n_batch
 
 /* --- serving ---------------------------------------------------------- */
 
-/* Asynchronous request: queued, admitted by memory, and executed by the
- * context's worker threads, which interleave work units of concurrent
- * requests on several streams.  bits and amps must stay valid until done.
- * The first call starts three workers; the context's HBM budget is then
- * split into four equal slots, one per worker and one for synchronous calls
- * on the same context (a larger cached synchronous workspace is released).
- * A request whose one-bitstring chunk does not fit a slot fails with
- * TNS_E_ADMISSION. */
+/* Asynchronous request (continuous batching).  A request is cut into work
+ * items, each a range of bitstrings times a range of slices (a block of the
+ * independent (bitstring, slice) units of the overlap paragraph's cutting),
+ * shaped at submission to about 4e13 contraction flops each and to fit
+ * memory.  The context's worker threads, one HIP stream and workspace each,
+ * take items round-robin over the active requests, so requests that arrive
+ * while others run are admitted as workers and memory free up and their
+ * items overlap on the device.  Memory: the first tns_submit starts the
+ * workers; a quarter of the context's HBM budget stays with synchronous
+ * calls on the same context (a larger cached synchronous workspace is
+ * released) and the rest is a pool the workers share; an item starts only
+ * when its workspace fits the pool beside the other workers' reservations,
+ * and while items wait for memory, idle workers return their cached
+ * workspace.  The partial sums of a request's slice ranges are added per
+ * bitstring in slice-range order, so a result does not depend on what else
+ * was served beside it.  bits and amps must stay valid until done.  A
+ * request of which one (bitstring, slice) unit does not fit the pool fails
+ * with TNS_E_ADMISSION. */
+
+/* Serving knobs, before the first tns_submit on ctx: n_workers (1..16, 0 =
+ * 3) and the contraction flops per work item (0 = 4e13; a small value cuts
+ * every request into single (bitstring, slice) units). */
+tns_status tns_serving_configure(tns_ctx *ctx, int32_t n_workers, double item_flops);
+
 tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                       const uint8_t *bits, double *amps, tns_request **out);
 tns_status tns_poll(tns_request *req, int *done);   /* *done = 1 when finished */

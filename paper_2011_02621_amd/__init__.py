@@ -8,6 +8,7 @@ turns error codes into exceptions.  If the shared library is missing it raises
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -26,7 +27,7 @@ PATH_MODE = {"greedy": 0, "algorithm1": 1}
 EXPORTED = ["tns_init", "tns_set_allocator", "tns_finalize", "tns_plan_opts_default",
             "tns_plan_create", "tns_plan_info_get", "tns_plan_destroy", "tns_amplitudes",
             "tns_amplitudes_sliced", "tns_sample_frugal",
-            "tns_submit", "tns_poll", "tns_wait", "tns_cancel", "tns_request_free",
+            "tns_serving_configure", "tns_submit", "tns_poll", "tns_wait", "tns_cancel", "tns_request_free",
             "tns_request_latency", "tns_path_search", "tns_last_error", "tns_version"]
 
 
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "tns_amplitudes": ([vp, vp, i64, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_amplitudes_sliced": ([vp, vp, i64, vp, i64, i64, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_sample_frugal": ([vp, vp, i64, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
+        "tns_serving_configure": ([vp, i32, ctypes.c_double], i32),
         "tns_submit": ([vp, vp, i64, vp, vp, ctypes.POINTER(vp)], i32),
         "tns_poll": ([vp, ctypes.POINTER(ctypes.c_int)], i32),
         "tns_wait": ([vp], i32),
@@ -207,6 +209,7 @@ def _arr(ptr, n, dtype):
 class Plan:
     def __init__(self, ctx: "Context", handle, keep):
         self.ctx, self._h, self._keep = ctx, handle, keep
+        ctx._plans.add(self)
         inf = self.info()
         self.n_qubits = inf.n_qubits
         self.n_open = len(inf.open_qubits)
@@ -282,6 +285,7 @@ class Context:
         self._h = h
         self.device = device
         self._alloc_cb = None
+        self._plans = weakref.WeakSet()   # closed before the context is
 
     def use_torch_allocator(self):
         """Route device allocations through torch's caching allocator."""
@@ -385,6 +389,11 @@ class Context:
             return out + ({f: getattr(st, f) for f, _ in _Stats._fields_},)
         return out
 
+    def configure_serving(self, n_workers: int = 0, item_flops: float = 0.0):
+        """Serving knobs (before the first submit): worker threads and the
+        contraction flops per work item."""
+        _check(load_library().tns_serving_configure(self._h, int(n_workers), float(item_flops)))
+
     def submit(self, plan: Plan, bits: np.ndarray) -> Request:
         bits = np.ascontiguousarray(bits, np.uint8).reshape(-1, plan.n_qubits)
         amps = np.zeros((bits.shape[0] << plan.n_open, 2), np.float64)
@@ -395,6 +404,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for p in list(self._plans):
+                p.close()
             _check(load_library().tns_finalize(self._h))
             self._h = None
 

@@ -2,6 +2,7 @@
 // the serving loop.  No C++ exception crosses into the caller.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <chrono>
@@ -47,10 +48,22 @@ static void hip_check(hipError_t e, const char *what) {
 }
 
 // ----------------------------------------------------------------------------
-// serving: requests are cut into chunks of bitstrings; worker threads (one
-// HIP stream and workspace each) take chunks round-robin over the active
-// requests, so a request arriving while others run is admitted as soon as a
-// worker frees up and its chunks overlap with theirs on the device.
+// serving.  A request is cut into work items, each a range of bitstrings
+// times a range of slices, i.e. a block of (bitstring, slice) units.  Worker
+// threads (one HIP stream and workspace each) take items round-robin over
+// the active requests, so a request that arrives while others run starts as
+// soon as a worker and the memory for one of its items are free, and its
+// items overlap with theirs on the device.
+//
+// Memory: the workers share a pool, the context's budget less the share kept
+// for synchronous calls.  A worker holds a reservation for the workspace it
+// caches; an item starts only when its workspace fits the pool beside the
+// other workers' reservations, and while items wait for memory, idle
+// workers give their cached workspace back.
+//
+// An item's shape is fixed when the request is submitted, so its partial
+// sums -- added per bitstring in slice-range order -- do not depend on how
+// the request's items interleave with other work.
 
 using clk = std::chrono::steady_clock;
 
@@ -59,10 +72,12 @@ struct Request {
     int64_t n = 0;
     const uint8_t *bits = nullptr;
     double *amps = nullptr;
-    int64_t chunk = 1;
-    int64_t next = 0;            // next bitstring to hand out
-    int64_t finished = 0;        // bitstrings completed
-    int running = 0;             // chunks in flight
+    int64_t nb_chunk = 1, ns_chunk = 1;   // bitstrings and slices per item
+    int64_t n_schunks = 1;               // slice ranges per bitstring range
+    int64_t n_items = 0, next_item = 0, finished_items = 0;
+    uint64_t item_bytes = 0;             // workspace of one item
+    std::vector<double> part;            // [n][n_schunks][opu][2] when n_schunks > 1
+    int running = 0;                     // items in flight
     volatile int cancel = 0;
     tns_status status = TNS_OK;
     bool done = false;
@@ -73,23 +88,38 @@ struct Request {
     std::condition_variable cv;
 };
 
+struct Item {
+    Request *r = nullptr;
+    int64_t b0 = 0, b1 = 0, s0 = 0, s1 = 0, si = 0;
+    bool release_first = false;
+    uint64_t budget = 0;
+};
+
 struct Server {
     Ctx *ctx = nullptr;
     std::vector<std::thread> workers;
     std::vector<void *> streams;
     std::vector<Workspace> ws;
+    std::vector<uint64_t> held;          // per worker: reserved workspace bytes
+    std::vector<const Plan *> held_plan; // per worker: plan its workspace was sized for
     std::mutex m;
     std::condition_variable cv;
     std::list<Request *> active;
     std::list<Request *>::iterator rr;
     bool stop = false;
-    uint64_t worker_budget = 0;
+    bool pressure = false;               // an item waits for memory
+    uint64_t pool = 0;                   // bytes the workers share
+    uint64_t reserved = 0;               // sum of held
+    uint64_t sync_budget = 0;            // workspace of synchronous calls
 
     void start(Ctx *c, int n_workers) {
         ctx = c;
-        worker_budget = ctx->budget / (uint64_t)(n_workers + 1);
+        sync_budget = ctx->budget / 4;
+        pool = ctx->budget - sync_budget;
         streams.resize(n_workers);
         ws.resize(n_workers);
+        held.assign(n_workers, 0);
+        held_plan.assign(n_workers, nullptr);
         for (int i = 0; i < n_workers; ++i) {
             hipStream_t s;
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -121,33 +151,56 @@ struct Server {
         }
     }
 
-    // called with m held
-    Request *pick(int64_t &b0, int64_t &b1) {
-        if (active.empty()) return nullptr;
-        auto it = rr == active.end() ? active.begin() : rr;
+    // called with m held: the next item a worker may run now, if any.
+    // Sets `newly_blocked` when this call is the one that raised `pressure`.
+    bool pick(int w, Item &it, bool &newly_blocked) {
+        newly_blocked = false;
+        if (active.empty()) return false;
+        auto cur = rr == active.end() ? active.begin() : rr;
+        bool blocked = false;
         for (size_t tries = 0; tries < active.size(); ++tries) {
-            Request *r = *it;
-            ++it;
-            if (it == active.end()) it = active.begin();
-            if (r->next < r->n && r->status == TNS_OK && !r->cancel) {
-                b0 = r->next;
-                b1 = std::min(r->n, b0 + r->chunk);
-                r->next = b1;
-                r->running++;
-                if (!r->started) {
-                    r->started = true;
-                    r->t_start = clk::now();
-                }
-                rr = it;
-                return r;
+            Request *r = *cur;
+            ++cur;
+            if (cur == active.end()) cur = active.begin();
+            if (r->next_item >= r->n_items || r->status != TNS_OK || r->cancel) continue;
+            const bool reuse = held_plan[w] == r->plan && held[w] >= r->item_bytes;
+            const uint64_t mine = reuse ? held[w] : r->item_bytes;
+            if (reserved - held[w] + mine > pool) {
+                blocked = true;
+                continue;
             }
+            it = Item{};
+            it.r = r;
+            it.release_first = !reuse && held[w] > 0;
+            reserved = reserved - held[w] + mine;
+            held[w] = mine;
+            held_plan[w] = r->plan;
+            it.budget = mine;
+            const int64_t i = r->next_item++;
+            it.si = i % r->n_schunks;
+            it.b0 = (i / r->n_schunks) * r->nb_chunk;
+            it.b1 = std::min(r->n, it.b0 + r->nb_chunk);
+            it.s0 = it.si * r->ns_chunk;
+            it.s1 = std::min(r->plan->n_slices, it.s0 + r->ns_chunk);
+            r->running++;
+            if (!r->started) {
+                r->started = true;
+                r->t_start = clk::now();
+            }
+            rr = cur;
+            return true;
         }
-        return nullptr;
+        if (blocked && !pressure) {
+            pressure = true;
+            newly_blocked = true;
+        }
+        return false;
     }
 
     void complete_if_done(Request *r) {
         // called with m held
-        bool over = r->running == 0 && (r->finished >= r->n || r->status != TNS_OK || r->cancel);
+        const bool over = r->running == 0 &&
+                          (r->finished_items >= r->n_items || r->status != TNS_OK || r->cancel);
         if (!over) return;
         // step the round-robin cursor off r before its node is erased
         auto it = std::find(active.begin(), active.end(), r);
@@ -156,9 +209,24 @@ struct Server {
         active.erase(it);
         // notify under r->m: a waiter that sees done may free r at once
         std::lock_guard<std::mutex> lk(r->m);
-        if (r->cancel && r->status == TNS_OK && r->finished < r->n) {
+        if (r->cancel && r->status == TNS_OK && r->finished_items < r->n_items) {
             r->status = TNS_E_CANCELLED;
             r->error = "request cancelled";
+        }
+        if (r->status == TNS_OK && r->n_schunks > 1) {
+            // partial sums of each bitstring, added in slice-range order
+            const int64_t opu = r->plan->out_per_unit, S = r->n_schunks;
+            for (int64_t b = 0; b < r->n; ++b)
+                for (int64_t j = 0; j < opu; ++j) {
+                    double re = 0, im = 0;
+                    for (int64_t k = 0; k < S; ++k) {
+                        const double *v = &r->part[((b * S + k) * opu + j) * 2];
+                        re += v[0];
+                        im += v[1];
+                    }
+                    r->amps[2 * (b * opu + j)] = re;
+                    r->amps[2 * (b * opu + j) + 1] = im;
+                }
         }
         r->t_end = clk::now();
         r->done = true;
@@ -167,21 +235,57 @@ struct Server {
 
     void loop(int wi) {
         (void)hipSetDevice(ctx->device);
+        std::vector<double> tmp;
         for (;;) {
-            Request *r = nullptr;
-            int64_t b0 = 0, b1 = 0;
+            Item it;
+            bool give_back = false;
             {
                 std::unique_lock<std::mutex> lk(m);
-                cv.wait(lk, [&] { return stop || (r = pick(b0, b1)) != nullptr; });
-                if (!r) return;
+                for (;;) {
+                    if (stop) return;
+                    bool newly = false;
+                    if (pick(wi, it, newly)) break;
+                    if (pressure && held[wi] > 0) {
+                        give_back = true;
+                        break;
+                    }
+                    // wake the idle workers that hold memory (once per rise of pressure)
+                    if (newly) cv.notify_all();
+                    cv.wait(lk);
+                }
             }
+            if (give_back) {
+                // another item waits for memory: return this worker's cache
+                ws[wi].release(ctx, streams[wi]);
+                {
+                    std::lock_guard<std::mutex> lk(m);
+                    reserved -= held[wi];
+                    held[wi] = 0;
+                    held_plan[wi] = nullptr;
+                    pressure = false;
+                }
+                cv.notify_all();
+                continue;
+            }
+            Request *r = it.r;
             tns_status st = TNS_OK;
             std::string err;
             RunStats rs;
             try {
-                run_amplitudes(ctx, *r->plan, b1 - b0, r->bits + b0 * r->plan->circ.n,
-                               r->amps + 2 * b0 * r->plan->out_per_unit,
-                               streams[wi], ws[wi], rs, &r->cancel, worker_budget);
+                if (it.release_first) ws[wi].release(ctx, streams[wi]);
+                const Plan &p = *r->plan;
+                const int64_t nb = it.b1 - it.b0, opu = p.out_per_unit;
+                double *out = r->amps + 2 * it.b0 * opu;
+                if (r->n_schunks > 1) {
+                    tmp.resize((size_t)(nb * opu * 2));
+                    out = tmp.data();
+                }
+                run_amplitudes(ctx, p, nb, r->bits + it.b0 * p.circ.n, out, streams[wi], ws[wi], rs,
+                               &r->cancel, it.budget, it.s0, it.s1);
+                if (r->n_schunks > 1)
+                    for (int64_t b = 0; b < nb; ++b)
+                        std::memcpy(&r->part[(((it.b0 + b) * r->n_schunks + it.si) * opu) * 2],
+                                    &tmp[b * opu * 2], sizeof(double) * 2 * opu);
             } catch (const Error &e) {
                 st = e.code;
                 err = e.what();
@@ -192,8 +296,9 @@ struct Server {
             if (st != TNS_OK) finish(r, st, err);
             {
                 std::lock_guard<std::mutex> lk(m);
+                // the workspace may have grown within this worker's reservation
                 r->running--;
-                if (st == TNS_OK) r->finished += b1 - b0;
+                if (st == TNS_OK) r->finished_items++;
                 complete_if_done(r);
             }
             cv.notify_all();
@@ -214,6 +319,30 @@ struct Server {
         complete_if_done(r);
     }
 };
+
+// Item shape of a request: about kItemFlops of contraction per item (a few
+// tenths of a second on the device), at most 64 bitstrings, and a workspace
+// that fits the pool.
+constexpr double kItemFlops = 4e13;
+
+static void shape_items(Request *r, const Server &sv, double item_flops) {
+    const double kItemFlops = item_flops > 0 ? item_flops : tns::kItemFlops;
+    const Plan &p = *r->plan;
+    const double per_slice = p.flops_per_amp / (double)p.n_slices;
+    int64_t nb = (int64_t)std::floor(kItemFlops / std::max(p.flops_per_amp, 1.0));
+    nb = std::max<int64_t>(1, std::min<int64_t>({nb, 64, r->n}));
+    int64_t ns = p.n_slices;
+    if (nb == 1) ns = std::max<int64_t>(1, std::min<int64_t>(p.n_slices, (int64_t)(kItemFlops / std::max(per_slice, 1.0))));
+    while (call_workspace_bytes(p, nb, ns, sv.pool) > sv.pool && (nb > 1 || ns > 1)) {
+        if (nb > 1) nb = (nb + 1) / 2;
+        else ns = (ns + 1) / 2;
+    }
+    r->nb_chunk = nb;
+    r->ns_chunk = ns;
+    r->n_schunks = (p.n_slices + ns - 1) / ns;
+    r->n_items = ((r->n + nb - 1) / nb) * r->n_schunks;
+    r->item_bytes = call_workspace_bytes(p, nb, ns, sv.pool);
+}
 
 }  // namespace tns
 
@@ -271,6 +400,10 @@ tns_status tns_set_allocator(tns_ctx *ctx, void *(*alloc)(size_t, void *, void *
 tns_status tns_finalize(tns_ctx *ctx) {
     return guard([&] {
         if (!ctx) return;
+        // a plan keeps device memory of its context: the context outlives it
+        if (ctx->live_plans > 0)
+            fail(TNS_E_INVALID_ARG, std::to_string(ctx->live_plans.load()) +
+                                        " plan(s) created on this context are alive; destroy them first");
         if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
         if (ctx->server) {
             ctx->server->shutdown();
@@ -329,6 +462,7 @@ tns_status tns_plan_create(tns_ctx *ctx, const tns_circuit_desc *desc, const tns
                 fail(TNS_E_OUT_OF_MEMORY, "one bitstring needs " + std::to_string(need) +
                                               " bytes of workspace, budget is " + std::to_string(ctx->budget));
             plan_device_setup(ctx, *p);
+            ctx->live_plans++;
         }
         *out = p.release();
     });
@@ -377,8 +511,10 @@ tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
 tns_status tns_plan_destroy(tns_plan *p) {
     return guard([&] {
         if (!p) return;
-        if (p->ctx && p->ctx->device >= 0) (void)hipSetDevice(p->ctx->device);
+        Ctx *owner = p->on_device ? p->ctx : nullptr;
+        if (owner && owner->device >= 0) (void)hipSetDevice(owner->device);
         plan_device_release(*p);
+        if (owner) owner->live_plans--;
         delete p;
     });
 }
@@ -407,7 +543,7 @@ static tns_status amplitudes_impl(tns_ctx *ctx, const tns_plan *plan, int64_t n,
             void *st = hip_stream ? hip_stream : ctx->stream;
             // once serving workers exist, synchronous calls take one slot's
             // share of the budget, like each worker
-            const uint64_t budget = ctx->server ? ctx->server->worker_budget : ctx->budget;
+            const uint64_t budget = ctx->server ? ctx->server->sync_budget : ctx->budget;
             run_amplitudes(ctx, *plan, n, bits, amps, st, ctx->ws, rs, nullptr, budget, slice_begin,
                            slice_end, frugal);
         }
@@ -488,27 +624,26 @@ tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8
             std::lock_guard<std::mutex> lk(ctx->mu);
             if (!ctx->server) {
                 ctx->server = new Server();
-                ctx->server->start(ctx, 3);
+                ctx->server->start(ctx, ctx->serving_workers > 0 ? ctx->serving_workers : 3);
                 // the synchronous workspace may have grown to the whole budget;
-                // from now on it shares the budget with the workers
-                if ((uint64_t)ctx->ws.bytes > ctx->server->worker_budget) {
+                // from now on it keeps a quarter and the workers share the rest
+                if ((uint64_t)ctx->ws.bytes > ctx->server->sync_budget) {
                     hip_check(hipSetDevice(ctx->device), "hipSetDevice");
                     ctx->ws.release(ctx, ctx->stream);
                 }
             }
         }
         Server *sv = ctx->server;
-        const uint64_t need = plan->bytes_per_bitstring + plan->bytes_per_unit;
-        if (need > sv->worker_budget)
-            fail(TNS_E_ADMISSION, "request needs " + std::to_string(need) + " bytes per chunk, a serving slot has " +
-                                      std::to_string(sv->worker_budget));
+        // admission: one (bitstring, slice) unit must fit the workers' pool
+        const uint64_t need = call_workspace_bytes(*plan, 1, 1, sv->pool);
+        if (need > sv->pool)
+            fail(TNS_E_ADMISSION, "one work unit needs " + std::to_string(need) +
+                                      " bytes, the serving pool has " + std::to_string(sv->pool));
         std::unique_ptr<tns_request> r(new tns_request());
         r->plan = plan;
         r->n = n;
         r->bits = bits;
         r->amps = amps;
-        int64_t fit = max_bitstrings_per_batch(ctx, *plan, sv->worker_budget);
-        r->chunk = std::max<int64_t>(1, std::min<int64_t>(fit, 64));
         r->t_submit = clk::now();
         if (n == 0) {
             r->done = true;
@@ -516,9 +651,24 @@ tns_status tns_submit(tns_ctx *ctx, const tns_plan *plan, int64_t n, const uint8
             *out = r.release();
             return;
         }
+        shape_items(r.get(), *sv, ctx->serving_item_flops);
+        if (r->n_schunks > 1)
+            r->part.assign((size_t)(n * r->n_schunks * plan->out_per_unit * 2), 0.0);
         tns_request *raw = r.release();
         sv->submit(raw);
         *out = raw;
+    });
+}
+
+tns_status tns_serving_configure(tns_ctx *ctx, int32_t n_workers, double item_flops) {
+    return guard([&] {
+        if (!ctx) fail(TNS_E_INVALID_ARG, "ctx is NULL");
+        if (n_workers < 0 || n_workers > 16) fail(TNS_E_INVALID_ARG, "n_workers must be 0..16");
+        if (!(item_flops >= 0)) fail(TNS_E_INVALID_ARG, "item_flops must be >= 0");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->server) fail(TNS_E_INVALID_ARG, "serving already started on this context");
+        ctx->serving_workers = n_workers;
+        ctx->serving_item_flops = item_flops;
     });
 }
 

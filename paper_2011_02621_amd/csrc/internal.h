@@ -3,6 +3,7 @@
 // prototypes shared by the host code and the HIP kernels.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -298,6 +299,9 @@ struct Ctx {
     Workspace ws;                        // workspace of synchronous calls
     int64_t peak_bytes = 0;
     Server *server = nullptr;
+    int serving_workers = 0;             // 0: three
+    double serving_item_flops = 0;       // 0: the default work per item
+    std::atomic<int> live_plans{0};      // plans holding device memory of this context
 };
 
 void *dev_alloc(Ctx *ctx, size_t bytes, void *stream);
@@ -333,6 +337,9 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
                     int64_t slice_end = -1, const FrugalAccept *frugal = nullptr);
 int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
+// Workspace bytes a fresh workspace holds after run_amplitudes(n bitstrings,
+// n_sl slices) under `budget`.
+uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t budget);
 
 // ----------------------------------------------------------------------------
 // kernel launchers (kernels_*.hip).  All take a hipStream_t as void*.

@@ -222,6 +222,32 @@ int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget) {
 
 enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_COUNT };
 
+uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t budget) {
+    // mirrors the slot sizes run_amplitudes takes from a fresh workspace
+    // (the first batch is the largest), in the workspace's own byte count
+    if (n <= 0) return 0;
+    const Circuit &c = p.circ;
+    const int64_t elem = p.precision != TNS_C128 ? 8 : 16;
+    const int64_t opu = p.out_per_unit;
+    auto slot = [](int64_t b) { return (uint64_t)std::max<int64_t>(b, 256); };
+    int64_t bra_total = 0, site_total = 0;
+    for (int q = 0; q < c.n; ++q) {
+        bra_total += 2 * p.bra.cap[q];
+        site_total += p.site_elems[q];
+    }
+    const int64_t nb = std::min<int64_t>(n, max_bitstrings_per_batch(nullptr, p, budget));
+    const int64_t units = nb * n_sl;
+    uint64_t used = slot(n * opu * 16) + slot(nb * c.n) + slot(bra_total * nb * 16) +
+                    slot(std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16) +
+                    slot(site_total * nb * elem) + slot(units * opu * 16);
+    const uint64_t left = budget > used ? budget - used : 0;
+    int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
+    const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max<int64_t>(p.unit_stride, 1));
+    G = std::max<int64_t>(1, std::min<int64_t>(std::min(G, fill), units));
+    used += 2 * slot(G * p.unit_stride * elem) + slot(G * p.max_b_elems * 2 * elem);
+    return used;
+}
+
 namespace {
 struct Timer {
     hipEvent_t e[2];
@@ -264,19 +290,38 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
     double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * opu * 16, stream);
     std::vector<char> is_open(c.n, 0);
     for (int q : c.open_qubits) is_open[q] = 1;
+    int64_t bra_total = 0, site_total = 0;
+    for (int q = 0; q < c.n; ++q) {
+        bra_total += 2 * p.bra.cap[q];
+        site_total += p.site_elems[q];
+    }
     for (int64_t b0 = 0; b0 < n; b0 += nb_max) {
         if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
         const int64_t nb = std::min(nb_max, n - b0);
+        const int64_t units = nb * n_sl;
+        // every workspace slot of the batch is taken before its first launch
         uint8_t *bits_dev = (uint8_t *)ws.get(ctx, S_BITS, (size_t)nb * c.n, stream);
+        double *bra = (double *)ws.get(ctx, S_BRA, (size_t)bra_total * nb * 16, stream);
+        double *vp = (double *)ws.get(ctx, S_VP, (size_t)std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16, stream);
+        char *sites = (char *)ws.get(ctx, S_SITES, (size_t)site_total * nb * elem, stream);
+        double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * opu * 16, stream);
+        const uint64_t used = ws.bytes;
+        const uint64_t left = budget > used ? budget - used : 0;
+        int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
+        // units per launch up to 2^30 boundary elements (measured on the
+        // 25-qubit workload, 4 -> 32 units per launch: +4.8 %, from shorter
+        // launch tails and fewer launches); the budget bounds it as well
+        const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max<int64_t>(p.unit_stride, 1));
+        G = std::max<int64_t>(1, std::min<int64_t>(std::min(G, fill), units));
+        const int64_t peak = p.unit_stride;
+        char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
+        char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
+        char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
         hip_check(hipMemcpyAsync(bits_dev, bits_host + b0 * c.n, (size_t)nb * c.n,
                                  hipMemcpyHostToDevice, (hipStream_t)stream), "bits upload");
 
         // ---- bra evolution, batched over bitstrings
         Timer tb(stream, timing);
-        int64_t bra_total = 0;
-        for (int q = 0; q < c.n; ++q) bra_total += 2 * p.bra.cap[q];
-        double *bra = (double *)ws.get(ctx, S_BRA, (size_t)bra_total * nb * 16, stream);
-        double *vp = (double *)ws.get(ctx, S_VP, (size_t)std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16, stream);
         SideBuffers sb;
         sb.buf[0].resize(c.n);
         sb.buf[1].resize(c.n);
@@ -299,9 +344,6 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
 
         // ---- overlap merge (Eq. (8))
         Timer tm(stream, timing);
-        int64_t site_total = 0;
-        for (int q = 0; q < c.n; ++q) site_total += p.site_elems[q];
-        char *sites = (char *)ws.get(ctx, S_SITES, (size_t)site_total * nb * elem, stream);
         std::vector<char *> site_ptr(c.n);
         {
             int64_t off = 0;
@@ -319,20 +361,6 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
 
         // ---- contraction of every (bitstring, slice) unit along the path
         Timer tc(stream, timing);
-        const int64_t units = nb * n_sl;
-        double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * opu * 16, stream);
-        const uint64_t used = ws.bytes;
-        const uint64_t left = budget > used ? budget - used : 0;
-        int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
-        // units per launch up to 2^30 boundary elements (measured on the
-        // 25-qubit workload, 4 -> 32 units per launch: +4.8 %, from shorter
-        // launch tails and fewer launches); the budget bounds it as well
-        const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max<int64_t>(p.unit_stride, 1));
-        G = std::max<int64_t>(1, std::min<int64_t>(std::min(G, fill), units));
-        const int64_t peak = p.unit_stride;
-        char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
-        char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
-        char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
         // optional per-class timing: events recorded around launches on this stream
         struct Ev { hipEvent_t a, b; int cls; double flops, bytes, mfma; };
         std::vector<Ev> evs;
