@@ -236,6 +236,8 @@ void tns_plan_opts_default(tns_plan_opts *opts);
 tns_status tns_plan_create(tns_ctx *ctx, const tns_circuit_desc *desc,
                            const tns_plan_opts *opts, tns_plan **out);
 tns_status tns_plan_info_get(const tns_plan *plan, tns_plan_info *out);
+/* Waits for the serving requests submitted on the plan to complete, then
+ * frees it. */
 tns_status tns_plan_destroy(tns_plan *plan);
 
 /* --- amplitudes ------------------------------------------------------- */

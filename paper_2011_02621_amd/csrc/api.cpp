@@ -137,6 +137,20 @@ struct Server {
         }
         cv.notify_all();
         for (auto &t : workers) t.join();
+        // requests left without workers end as cancelled (their plans are
+        // destroyed first, so normally none is left)
+        for (Request *r : active) {
+            r->plan->serving_in_flight--;
+            std::lock_guard<std::mutex> lk(r->m);
+            if (r->status == TNS_OK) {
+                r->status = TNS_E_CANCELLED;
+                r->error = "context finalized";
+            }
+            r->t_end = clk::now();
+            r->done = true;
+            r->cv.notify_all();
+        }
+        active.clear();
         for (size_t i = 0; i < streams.size(); ++i) {
             ws[i].release(ctx, streams[i]);
             (void)hipStreamDestroy((hipStream_t)streams[i]);
@@ -207,6 +221,8 @@ struct Server {
         if (it == active.end()) return;   // already completed
         if (rr == it) ++rr;
         active.erase(it);
+        r->plan->serving_in_flight--;
+        cv.notify_all();   // a tns_plan_destroy may wait for this plan's requests
         // notify under r->m: a waiter that sees done may free r at once
         std::lock_guard<std::mutex> lk(r->m);
         if (r->cancel && r->status == TNS_OK && r->finished_items < r->n_items) {
@@ -308,6 +324,7 @@ struct Server {
     void submit(Request *r) {
         {
             std::lock_guard<std::mutex> lk(m);
+            r->plan->serving_in_flight++;
             active.push_back(r);
         }
         cv.notify_all();
@@ -512,6 +529,12 @@ tns_status tns_plan_destroy(tns_plan *p) {
     return guard([&] {
         if (!p) return;
         Ctx *owner = p->on_device ? p->ctx : nullptr;
+        if (owner && owner->server) {
+            // requests on this plan are still being served: wait for them
+            Server *sv = owner->server;
+            std::unique_lock<std::mutex> lk(sv->m);
+            sv->cv.wait(lk, [&] { return p->serving_in_flight.load() == 0; });
+        }
         if (owner && owner->device >= 0) (void)hipSetDevice(owner->device);
         plan_device_release(*p);
         if (owner) owner->live_plans--;

@@ -269,6 +269,7 @@ struct Plan {
     int64_t bytes_per_unit = 0;
     int64_t bytes_per_bitstring = 0;
     int64_t bra_scratch_elems = 0;       // V' scratch per bitstring (complex128)
+    mutable std::atomic<int> serving_in_flight{0};   // submitted requests not yet complete
 };
 
 // ----------------------------------------------------------------------------
