@@ -264,6 +264,31 @@ tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n,
                                  const uint8_t *bits, int64_t slice_begin, int64_t slice_end,
                                  double *amps, void *hip_stream, tns_stats *stats);
 
+/* Allocation-free variant of tns_amplitudes, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It computes the same amplitudes as
+ * tns_amplitudes (same kernels), with every intermediate -- bra tensors,
+ * merged site tensors, boundary tensors, GEMM operands, per-slice partial
+ * sums -- placed in a static device array of TNS_NOALLOC_SCRATCH_BYTES per
+ * GPU that exists from library load to process end; the call allocates and
+ * frees nothing and does not synchronise: it only enqueues work on
+ * hip_stream (NULL = the context's stream) and returns.
+ *   bits_dev  device array [n][n_qubits], bit = byte & 1; read in place.
+ *   amps_dev  device array [n][2^n_open] of complex128 (re, im) pairs,
+ *             written in place; valid once the stream reaches that point.
+ * Both stay owned by the caller and must stay valid until the stream has
+ * run the work.  The plan must have been created on ctx (plan creation
+ * itself allocates).  Errors: TNS_E_INVALID_ARG as tns_amplitudes;
+ * TNS_E_OUT_OF_MEMORY, before any launch, when the plan's workspace for one
+ * bitstring does not fit the static array (larger batches are split into
+ * batches that fit).  Every call on one GPU shares that GPU's array, and
+ * the array keeps the last call's contents: calls whose work overlaps on the
+ * device race (two streams, or two contexts on one GPU); order them on one
+ * stream or synchronise between them. */
+#define TNS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tns_status tns_amplitudes_noalloc(tns_ctx *ctx, const tns_plan *plan, int64_t n,
+                                  const uint8_t *bits_dev, double *amps_dev, void *hip_stream);
+
 /* Frugal rejection sampling from correlated batches.  The tensor network's
  * advantage over a state vector includes simulating measurements
  * (introduction); with open qubits (tns_plan_opts.open_qubits, k of them)

@@ -26,7 +26,7 @@ PATH_MODE = {"greedy": 0, "algorithm1": 1}
 
 EXPORTED = ["tns_init", "tns_set_allocator", "tns_finalize", "tns_plan_opts_default",
             "tns_plan_create", "tns_plan_info_get", "tns_plan_destroy", "tns_amplitudes",
-            "tns_amplitudes_sliced", "tns_sample_frugal",
+            "tns_amplitudes_sliced", "tns_amplitudes_noalloc", "tns_sample_frugal",
             "tns_serving_configure", "tns_submit", "tns_poll", "tns_wait", "tns_cancel", "tns_request_free",
             "tns_request_latency", "tns_path_search", "tns_last_error", "tns_version"]
 
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
         "tns_plan_destroy": ([vp], i32),
         "tns_amplitudes": ([vp, vp, i64, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_amplitudes_sliced": ([vp, vp, i64, vp, i64, i64, vp, vp, ctypes.POINTER(_Stats)], i32),
+        "tns_amplitudes_noalloc": ([vp, vp, i64, vp, vp, vp], i32),
         "tns_sample_frugal": ([vp, vp, i64, vp, vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(_Stats)], i32),
         "tns_serving_configure": ([vp, i32, ctypes.c_double], i32),
         "tns_submit": ([vp, vp, i64, vp, vp, ctypes.POINTER(vp)], i32),
@@ -369,6 +370,16 @@ class Context:
         if stats:
             return out, {f: getattr(st, f) for f, _ in _Stats._fields_}
         return out
+
+    def amplitudes_noalloc(self, plan: Plan, n: int, bits_dev: int, amps_dev: int,
+                           stream: Optional[int] = None):
+        """Allocation-free amplitudes: ``bits_dev`` (uint8 [n][N]) and
+        ``amps_dev`` (complex128 [n][2^open]) are device addresses owned by
+        the caller; the work is only enqueued on ``stream``."""
+        _check(load_library().tns_amplitudes_noalloc(self._h, plan._h, int(n), bits_dev, amps_dev,
+                                                     stream))
+
+    NOALLOC_SCRATCH_BYTES = 64 << 20
 
     def sample_frugal(self, plan: Plan, fixed_bits: np.ndarray, uniforms: np.ndarray,
                       m_bound: float = 10.0, stream: Optional[int] = None, stats: bool = False):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libtns.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels_evolve.hip", "kernels_contract.hip", "kernels_sample.hip"]
+HIP_SOURCES = ["kernels_evolve.hip", "kernels_contract.hip", "kernels_sample.hip", "scratch.hip"]
 CXX_SOURCES = ["planner.cpp", "runtime.cpp", "api.cpp"]
 
 HIPCC = os.path.join(ROCM, "bin", "hipcc")

@@ -386,6 +386,7 @@ tns_status tns_init(int device, uint64_t hbm_budget_bytes, tns_ctx **out) {
             hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
             if (device >= count) fail(TNS_E_INVALID_ARG, "no such device");
             hip_check(hipSetDevice(device), "hipSetDevice");
+            scratch_setup(device);   // tns_amplitudes_noalloc's workspace on this device
             hipStream_t s;
             hip_check(hipStreamCreate(&s), "hipStreamCreate");
             c->stream = s;
@@ -610,6 +611,29 @@ tns_status tns_amplitudes_sliced(tns_ctx *ctx, const tns_plan *plan, int64_t n, 
         return TNS_E_INVALID_ARG;
     }
     return amplitudes_impl(ctx, plan, n, bits, slice_begin, slice_end, amps, hip_stream, stats);
+}
+
+tns_status tns_amplitudes_noalloc(tns_ctx *ctx, const tns_plan *plan, int64_t n,
+                                  const uint8_t *bits_dev, double *amps_dev, void *hip_stream) {
+    return guard([&] {
+        if (!ctx || !plan) fail(TNS_E_INVALID_ARG, "ctx or plan is NULL");
+        if (n < 0) fail(TNS_E_INVALID_ARG, "n must be >= 0");
+        if (n > 0 && (!bits_dev || !amps_dev)) fail(TNS_E_INVALID_ARG, "bits_dev or amps_dev is NULL");
+        if (ctx->device < 0) fail(TNS_E_NO_DEVICE, "planning-only context cannot compute amplitudes");
+        if (!plan->on_device || plan->ctx != ctx) fail(TNS_E_INVALID_ARG, "plan was not created on this context");
+        if (n == 0) return;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        char *base = (char *)scratch_device_ptr(ctx->device);
+        if (!base) fail(TNS_E_DEVICE, "static workspace not set up on this device");
+        Workspace arena;
+        arena.arena = base;
+        arena.arena_cap = kNoAllocScratchBytes;
+        RunStats rs;
+        void *st = hip_stream ? hip_stream : ctx->stream;
+        run_amplitudes(ctx, *plan, n, nullptr, nullptr, st, arena, rs, nullptr, kNoAllocScratchBytes,
+                       0, -1, nullptr, bits_dev, amps_dev);
+    });
 }
 
 tns_status tns_sample_frugal(tns_ctx *ctx, const tns_plan *plan, int64_t n_batches,

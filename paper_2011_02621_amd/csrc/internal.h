@@ -279,12 +279,26 @@ struct Ctx;
 
 // Workspace buffers owned by one executor (the synchronous path or one
 // serving stream); grown on demand, reused across calls.
+// In arena mode (arena != nullptr) the slots are carved once, in order, out
+// of a caller-provided device region of arena_cap bytes, and nothing is
+// allocated or freed: a slot that would not fit fails with
+// TNS_E_OUT_OF_MEMORY.
 struct Workspace {
     std::vector<DeviceBuf> bufs;
     int64_t bytes = 0;
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_top = 0;
     void *get(Ctx *ctx, int slot, size_t bytes, void *stream);
     void release(Ctx *ctx, void *stream);
 };
+
+// Device address of the static workspace of tns_amplitudes_noalloc on one
+// device (scratch.hip).  scratch_setup looks it up once per device and must
+// run with that device current; scratch_device_ptr returns the stored address
+// (nullptr before setup).
+constexpr size_t kNoAllocScratchBytes = TNS_NOALLOC_SCRATCH_BYTES;
+void scratch_setup(int device);
+void *scratch_device_ptr(int device);
 
 struct Server;
 
@@ -333,10 +347,15 @@ struct FrugalAccept {
 
 // Amplitudes of bitstrings [0, n) into host amps (complex128 pairs), using at
 // most `budget` bytes of workspace beyond the plan's resident tensors.
+// With bits_dev / amps_dev (device arrays of the same layouts) the bits are
+// read in place and the amplitudes written in place, without host copies or
+// a final synchronisation (the call only enqueues); bits_host / amps_host
+// are then unused.
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
-                    int64_t slice_end = -1, const FrugalAccept *frugal = nullptr);
+                    int64_t slice_end = -1, const FrugalAccept *frugal = nullptr,
+                    const uint8_t *bits_dev = nullptr, double *amps_dev = nullptr);
 int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
 // Workspace bytes a fresh workspace holds after run_amplitudes(n bitstrings,
 // n_sl slices) under `budget`.

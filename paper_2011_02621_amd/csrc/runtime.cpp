@@ -41,6 +41,22 @@ void dev_free(Ctx *ctx, void *p, void *stream) {
 void *Workspace::get(Ctx *ctx, int slot, size_t need, void *stream) {
     if ((int)bufs.size() <= slot) bufs.resize(slot + 1);
     DeviceBuf &b = bufs[slot];
+    if (arena) {
+        if (b.ptr) {
+            if (b.bytes < need) fail(TNS_E_OUT_OF_MEMORY, "static workspace slot cannot grow");
+            return b.ptr;
+        }
+        const size_t len = (std::max(need, (size_t)256) + 255) & ~(size_t)255;
+        if (len > arena_cap - arena_top)
+            fail(TNS_E_OUT_OF_MEMORY, "the call needs more than the " + std::to_string(arena_cap) +
+                                      " bytes of the static workspace (" + std::to_string(arena_top) +
+                                      " in use, " + std::to_string(len) + " more asked)");
+        b.ptr = arena + arena_top;
+        b.bytes = len;
+        arena_top += len;
+        bytes += len;
+        return b.ptr;
+    }
     if (b.bytes < need) {
         if (b.ptr) {
             hip_check(hipStreamSynchronize((hipStream_t)stream), "workspace sync");
@@ -60,6 +76,12 @@ void *Workspace::get(Ctx *ctx, int slot, size_t need, void *stream) {
 }
 
 void Workspace::release(Ctx *ctx, void *stream) {
+    if (arena) {
+        bufs.clear();
+        bytes = 0;
+        arena_top = 0;
+        return;
+    }
     if (!bufs.empty()) (void)hipStreamSynchronize((hipStream_t)stream);
     for (auto &b : bufs) dev_free(ctx, b.ptr, stream);
     bufs.clear();
@@ -276,7 +298,8 @@ struct Timer {
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin,
-                    int64_t slice_end, const FrugalAccept *frugal) {
+                    int64_t slice_end, const FrugalAccept *frugal, const uint8_t *bits_dev_in,
+                    double *amps_dev_out) {
     const Circuit &c = p.circ;
     if (slice_end < 0) slice_end = p.n_slices;
     const int64_t n_sl = slice_end - slice_begin;   // slices computed per bitstring
@@ -287,7 +310,8 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
     const bool timing = st.profile;
 
     const int64_t opu = p.out_per_unit;   // amplitudes per bitstring (open qubits)
-    double *amps_dev = (double *)ws.get(ctx, S_AMPS, (size_t)n * opu * 16, stream);
+    double *amps_dev = amps_dev_out ? amps_dev_out
+                                    : (double *)ws.get(ctx, S_AMPS, (size_t)n * opu * 16, stream);
     std::vector<char> is_open(c.n, 0);
     for (int q : c.open_qubits) is_open[q] = 1;
     int64_t bra_total = 0, site_total = 0;
@@ -300,7 +324,8 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         const int64_t nb = std::min(nb_max, n - b0);
         const int64_t units = nb * n_sl;
         // every workspace slot of the batch is taken before its first launch
-        uint8_t *bits_dev = (uint8_t *)ws.get(ctx, S_BITS, (size_t)nb * c.n, stream);
+        uint8_t *bits_dev = bits_dev_in ? (uint8_t *)bits_dev_in + b0 * c.n
+                                        : (uint8_t *)ws.get(ctx, S_BITS, (size_t)nb * c.n, stream);
         double *bra = (double *)ws.get(ctx, S_BRA, (size_t)bra_total * nb * 16, stream);
         double *vp = (double *)ws.get(ctx, S_VP, (size_t)std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16, stream);
         char *sites = (char *)ws.get(ctx, S_SITES, (size_t)site_total * nb * elem, stream);
@@ -317,8 +342,9 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
         char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
         char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
-        hip_check(hipMemcpyAsync(bits_dev, bits_host + b0 * c.n, (size_t)nb * c.n,
-                                 hipMemcpyHostToDevice, (hipStream_t)stream), "bits upload");
+        if (!bits_dev_in)
+            hip_check(hipMemcpyAsync(bits_dev, bits_host + b0 * c.n, (size_t)nb * c.n,
+                                     hipMemcpyHostToDevice, (hipStream_t)stream), "bits upload");
 
         // ---- bra evolution, batched over bitstrings
         Timer tb(stream, timing);
@@ -475,6 +501,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         hip_check(hipMemcpyAsync(frugal->flags, f_dev, (size_t)na, hipMemcpyDeviceToHost,
                                  (hipStream_t)stream), "flags download");
     }
+    if (amps_dev_out) return;   // results stay on the device, ordered on `stream`
     hip_check(hipMemcpyAsync(amps_host, amps_dev, (size_t)n * opu * 16, hipMemcpyDeviceToHost,
                              (hipStream_t)stream), "amplitude download");
     hip_check(hipStreamSynchronize((hipStream_t)stream), "amplitudes");

@@ -1,0 +1,73 @@
+"""tns_amplitudes_noalloc (static workspace, no allocation) against
+tns_amplitudes, both through the C ABI, on two calls in a row (the second
+smaller), plus its size limit."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2011_02621_amd as T
+from circuits import config, bitstrings
+from oracle.metrics import compare
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-4}
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _noalloc(ctx, plan, bits, torch):
+    n = bits.shape[0]
+    per = 1 << plan.n_open
+    bd = torch.from_numpy(np.ascontiguousarray(bits, np.uint8)).to("cuda")
+    ad = torch.full((n * per, 2), float("nan"), dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    ctx.amplitudes_noalloc(plan, n, bd.data_ptr(), ad.data_ptr(), s.cuda_stream)
+    s.synchronize()
+    return ad.cpu().numpy().view(np.complex128).reshape(-1)
+
+
+@pytest.mark.parametrize("prec,open_qubits", [("c128", None), ("c64", None), ("c64", [11, 0])])
+def test_noalloc_matches_amplitudes(prec, open_qubits):
+    import torch
+    c, bits = config("grid3x4_d8")
+    ctx = T.Context(0)
+    try:
+        p = ctx.plan(c, precision=prec, open_qubits=open_qubits)
+        for label, b in (("64 bitstrings", bits), ("16 others", bitstrings(12, 16, 7))):
+            say("noalloc", prec, open_qubits, label)
+            want = ctx.amplitudes(p, b).reshape(-1)
+            got = _noalloc(ctx, p, b, torch)
+            m = compare(want, got, c.n)
+            say("noalloc", prec, label, "rel_l2 %.3e exact %s" % (m["rel_l2"], bool(np.array_equal(got, want))))
+            assert m["rel_l2"] <= TOL[prec] and m["max_scaled"] <= 10 * TOL[prec], m
+        p.close()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_rejects_plans_beyond_the_static_workspace():
+    import torch
+    c, bits = config("grid5x5_d10", n_bits=1)
+    ctx = T.Context(0)
+    try:
+        p = ctx.plan(c, precision="c64")
+        assert p.info().device_bytes_per_unit > T.Context.NOALLOC_SCRATCH_BYTES
+        bd = torch.from_numpy(bits).to("cuda")
+        ad = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        say("noalloc beyond the static workspace")
+        with pytest.raises(T.TnsError) as e:
+            ctx.amplitudes_noalloc(p, 1, bd.data_ptr(), ad.data_ptr(),
+                                   torch.cuda.current_stream().cuda_stream)
+        assert e.value.name == "TNS_E_OUT_OF_MEMORY"
+        torch.cuda.synchronize()
+        # nothing was launched: the output is untouched
+        assert float(ad.abs().sum()) == 0.0
+        p.close()
+    finally:
+        ctx.close()
