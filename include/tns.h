@@ -130,6 +130,10 @@ typedef struct {
                                   one contraction yields the 2^n_open amplitudes of all
                                   bitstrings that agree outside these qubits (the rest
                                   of the network, and its contraction, is shared). */
+    int32_t path_branches;     /* 1 (default) = relax the linear path into a main path with
+                                  side branches where that lowers the summed cost (several
+                                  main paths, the relaxation of the single main path that the
+                                  supplement leaves open); 0 = one linear path */
 } tns_plan_opts;
 
 /* Description of a plan.  Pointers refer to plan-owned memory, valid until
@@ -172,6 +176,13 @@ typedef struct {
     tns_precision precision;
     int32_t n_open;                 /* open qubits; each input bitstring yields 2^n_open amplitudes */
     const int32_t *open_qubits;     /* [n_open] */
+    int32_t n_branches;             /* side branches of the path (tns_plan_opts.path_branches) */
+    const int32_t *branch_windows;  /* [n_branches][2]: positions [a, b) of `path` contracted as
+                                       one branch (in path order) and absorbed by the main path
+                                       just before it reaches position b */
+    const int32_t *step_chain;      /* [n_steps] 0 main path, w + 1 a step of branch w */
+    double linear_score;            /* sum of M*K*N of one slice along `path` as a single linear
+                                       path (path_score is that of the plan with its branches) */
 } tns_plan_info;
 
 typedef struct {

@@ -85,3 +85,96 @@ def subset_dp(n, edges, dims):
                     val = c
             best[mask] = val
     return best[full]
+
+
+def tree_score(order, windows, n, edges, dims):
+    """(score, largest main-path intermediate, largest branch tensor) of a
+    linear order relaxed into a main path with side branches ("several main
+    paths", which the supplement leaves open beside its single main path).
+
+    Each window (a, b) of positions of ``order`` (a >= 1, windows disjoint)
+    is contracted by its own linear path in the order's sequence; the main
+    path takes the remaining positions in sequence and absorbs a branch's
+    tensor whole just before it reaches a position >= b (branches whose
+    window reaches the end are absorbed after the last main site, by
+    increasing b).  Every pairwise step costs Cost() above."""
+    legs = _legs(n, edges)
+    size = lambda s: math.prod(dims[e] for e in s)
+    inwin = {}
+    for w, (a, b) in enumerate(windows):
+        for i in range(a, b):
+            inwin[i] = w
+    total, biggest, branch_biggest = 0, 0, 0
+
+    def branch(w):
+        nonlocal total, branch_biggest
+        a, b = windows[w]
+        t = set(legs[order[a]])
+        branch_biggest = max(branch_biggest, size(t))
+        for i in range(a + 1, b):
+            total += cost(t, legs[order[i]], dims)
+            t = t ^ set(legs[order[i]])
+            branch_biggest = max(branch_biggest, size(t))
+        return t
+
+    pending = sorted(range(len(windows)), key=lambda w: windows[w][1])
+    cur = None
+    for i, q in enumerate(order):
+        if i in inwin:
+            continue
+        while cur is not None and pending and windows[pending[0]][1] <= i:
+            x = branch(pending.pop(0))
+            total += cost(cur, x, dims)
+            cur = cur ^ x
+            biggest = max(biggest, size(cur))
+        if cur is None:
+            cur = set(legs[q])
+            biggest = size(cur)
+        else:
+            total += cost(cur, legs[q], dims)
+            cur = cur ^ set(legs[q])
+            biggest = max(biggest, size(cur))
+    while pending:
+        x = branch(pending.pop(0))
+        total += cost(cur, x, dims)
+        cur = cur ^ x
+        biggest = max(biggest, size(cur))
+    return total, biggest, branch_biggest
+
+
+def tree_optimum(n, edges, dims):
+    """Least summed Cost over every binary contraction tree (any pairing of
+    any two disjoint groups at each step), by recursion over subsets: the
+    cost of a group is the best split into two non-empty parts plus the
+    Cost of contracting their two tensors.  A lower bound for linear paths
+    and for main paths with branches alike."""
+    if n > 12:
+        raise ValueError("tree optimum is limited to N <= 12")
+    legs = _legs(n, edges)
+    open_of = {}
+
+    def open_legs(mask):
+        if mask not in open_of:
+            cnt = {}
+            for q in range(n):
+                if mask >> q & 1:
+                    for e in legs[q]:
+                        cnt[e] = cnt.get(e, 0) + 1
+            open_of[mask] = frozenset(e for e, c in cnt.items() if c == 1)
+        return open_of[mask]
+
+    best = {1 << q: 0 for q in range(n)}
+    for size_ in range(2, n + 1):
+        for combo in itertools.combinations(range(n), size_):
+            mask = sum(1 << q for q in combo)
+            val = None
+            sub = (mask - 1) & mask
+            while sub:
+                rest = mask ^ sub
+                if sub < rest:   # each unordered split once
+                    c = best[sub] + best[rest] + cost(open_legs(sub), open_legs(rest), dims)
+                    if val is None or c < val:
+                        val = c
+                sub = (sub - 1) & mask
+            best[mask] = val
+    return best[(1 << n) - 1]

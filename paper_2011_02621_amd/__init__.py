@@ -60,7 +60,7 @@ class _PlanOpts(ctypes.Structure):
                 ("cut_edges", ctypes.c_void_p), ("max_intermediate_elems", ctypes.c_uint64),
                 ("svd_rel_cutoff", ctypes.c_double), ("max_search_states", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("n_open", ctypes.c_int32),
-                ("open_qubits", ctypes.c_void_p)]
+                ("open_qubits", ctypes.c_void_p), ("path_branches", ctypes.c_int32)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -85,7 +85,11 @@ class _PlanInfo(ctypes.Structure):
                 ("search_states", ctypes.c_int64), ("max_rank_used", ctypes.c_int32),
                 ("fidelity", ctypes.c_double), ("n_samples", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("n_open", ctypes.c_int32),
-                ("open_qubits", ctypes.POINTER(ctypes.c_int32))]
+                ("open_qubits", ctypes.POINTER(ctypes.c_int32)),
+                ("n_branches", ctypes.c_int32),
+                ("branch_windows", ctypes.POINTER(ctypes.c_int32)),
+                ("step_chain", ctypes.POINTER(ctypes.c_int32)),
+                ("linear_score", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -199,6 +203,9 @@ class PlanInfo:
     n_samples: float
     precision: int
     open_qubits: np.ndarray
+    branch_windows: np.ndarray   # [n_branches][2]
+    step_chain: np.ndarray
+    linear_score: float
 
 
 def _arr(ptr, n, dtype):
@@ -229,7 +236,9 @@ class Plan:
             inf.gemm_bytes_per_amp, inf.permute_bytes_per_amp, inf.path_score, inf.peak_elems,
             inf.device_bytes_resident, inf.device_bytes_per_unit, inf.n_fused_ket,
             inf.n_fused_bra, bool(inf.search_complete), inf.search_states, inf.max_rank_used,
-            inf.fidelity, inf.n_samples, inf.precision, _arr(inf.open_qubits, inf.n_open, np.int32))
+            inf.fidelity, inf.n_samples, inf.precision, _arr(inf.open_qubits, inf.n_open, np.int32),
+            _arr(inf.branch_windows, 2 * inf.n_branches, np.int32).reshape(-1, 2),
+            _arr(inf.step_chain, ns, np.int32), inf.linear_score)
 
     def close(self):
         if self._h:
@@ -313,7 +322,8 @@ class Context:
              path_mode: str = "algorithm1", max_rank: int = 0, path_assumptions: bool = True,
              cuts: Optional[Sequence[int]] = None, max_intermediate_elems: int = 1 << 32,
              precision: str = "c128", max_search_states: int = 0,
-             svd_rel_cutoff: float = 1e-12, open_qubits: Optional[Sequence[int]] = None) -> Plan:
+             svd_rel_cutoff: float = 1e-12, open_qubits: Optional[Sequence[int]] = None,
+             branches: bool = True) -> Plan:
         lib = load_library()
         n, edges, gates = _circuit_arrays(circ)
         desc = _CircuitDesc(n, edges.shape[0], edges.ctypes.data, gates.shape[0], gates.ctypes.data)
@@ -339,6 +349,7 @@ class Context:
         o.svd_rel_cutoff = float(svd_rel_cutoff)
         o.max_search_states = int(max_search_states)
         o.precision = PRECISION[precision]
+        o.path_branches = 1 if branches else 0
         if open_qubits:
             oq = np.ascontiguousarray(open_qubits, np.int32)
             keep.append(oq)

@@ -452,6 +452,7 @@ void tns_plan_opts_default(tns_plan_opts *o) {
     o->precision = TNS_C128;
     o->n_open = 0;
     o->open_qubits = nullptr;
+    o->path_branches = 1;
 }
 
 tns_status tns_plan_create(tns_ctx *ctx, const tns_circuit_desc *desc, const tns_plan_opts *opts,
@@ -523,6 +524,10 @@ tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
         o->precision = (tns_precision)p->precision;
         o->n_open = p->circ.n_open;
         o->open_qubits = p->circ.open_qubits.data();
+        o->n_branches = (int32_t)p->branches.size();
+        o->branch_windows = p->info_branch_windows.data();
+        o->step_chain = p->info_chain.data();
+        o->linear_score = p->linear_score;
     });
 }
 

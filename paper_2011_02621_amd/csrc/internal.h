@@ -145,7 +145,11 @@ inline bool small_rows_fits(int64_t M, int64_t K, int64_t N, int64_t csize) {
 }
 
 struct Step {
-    int site = -1;                       // tensor absorbed (i_{m+1}); for step 0 the start
+    int chain = 0;                       // 0: the main path; w + 1: branch w
+    bool start = false;                  // the chain's first tensor, gathered from `site`
+    int site = -1;                       // site tensor absorbed (i_{m+1}), or the start site
+    int branch = -1;                     // >= 0: absorbs that branch's tensor instead of a site
+    int prev = -1;                       // step that produced this step's A operand
     std::vector<int> t_legs;             // boundary legs before the step (storage order)
     bool permute = false;
     bool permute_fused = false;          // done by the previous step's GEMM store
@@ -156,7 +160,7 @@ struct Step {
     int sc_shift = 0, sc_mfast = 0;
     std::vector<int> m_legs, k_legs, n_legs;
     int64_t M = 1, K = 1, N = 1;
-    int kernel = 0;                      // 0 MFMA GEMM, 1 small, 2 final dot
+    int kernel = 0;                      // 0 MFMA GEMM, 1 small, 2 final dot, 3 MFMA GEMM (3 products)
     Gather bgather;                      // site tensor -> B[n][k] (k fastest)
     int64_t out_elems = 0;               // M * N
 };
@@ -197,6 +201,12 @@ double path_score(int n, const std::vector<std::pair<int, int>> &edges,
                   double *peak, int *max_rank);
 
 void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p);
+std::vector<std::pair<int, int>> choose_branches(const Circuit &c, const std::vector<double> &d,
+                                                 const std::vector<int> &order, double log2_limit,
+                                                 double log2_branch_limit, double *score_out);
+// branch tensors stay below this many elements (their buffer is a third
+// boundary buffer of each work unit)
+constexpr int64_t kBranchPeakElems = (int64_t)1 << 28;
 
 // ----------------------------------------------------------------------------
 // the plan
@@ -236,13 +246,19 @@ struct Plan {
 
     // path and steps
     PathResult path;
+    // branches (several main paths): windows [a, b) of path.order contracted
+    // by their own linear path and absorbed whole by the main path
+    std::vector<std::pair<int, int>> branches;
+    double linear_score = 0;             // sum of M K N of the single linear path
     // Algorithm 1 searches that built the final path: all finished within
     // their state budget, and the states they popped
     bool search_complete = true;
     int64_t search_states = 0;
     std::vector<Step> steps;
     int64_t peak_elems = 0;
+    int64_t branch_peak_elems = 0;       // largest tensor of a branch
     int64_t unit_stride = 0;             // boundary buffer stride per unit (peak, 32-aligned)
+    int64_t branch_stride = 0;           // branch buffer stride per unit (32-aligned)
     int64_t max_b_elems = 0;             // largest B operand (complex elements)
     double flops_per_amp = 0, gemm_bytes_per_amp = 0, permute_bytes_per_amp = 0;
     double path_score = 0;
@@ -254,7 +270,7 @@ struct Plan {
 
     // info arrays exposed through tns_plan_info
     std::vector<int64_t> info_m, info_k, info_n;
-    std::vector<int32_t> info_kernel, info_permute, info_path;
+    std::vector<int32_t> info_kernel, info_permute, info_path, info_chain, info_branch_windows;
     double fidelity = 0, n_samples = 0;
 
     // device state

@@ -675,24 +675,218 @@ bool build_scatter(const Gather &g, int64_t M, int64_t N, Step &s) {
 
 }  // namespace
 
+// ----------------------------------------------------------------------------
+// Several main paths.  Algorithm 1 keeps one main path (assumption 3 lets a
+// single isolated qubit wait to be joined), and the supplement notes that
+// nothing guarantees one main path to be the cheaper choice.  Here a linear
+// order is relaxed into a main path with side branches: a window [a, b) of
+// positions of the order (a >= 1) is contracted by its own linear path, in
+// the same order, and the main path absorbs the branch's tensor as one
+// operand just before it reaches position b (windows ending at the last
+// position are absorbed at the end).  Every step keeps the supplement's
+// Cost(A, B): the product of the dimensions of the bonds either operand
+// carries.
+
+namespace {
+
+struct LegSet {
+    // bonds of a tensor as a bit set over edge ids (at most 256 edges)
+    uint64_t w[4] = {0, 0, 0, 0};
+    void flip(int e) { w[e >> 6] ^= 1ULL << (e & 63); }
+    bool has(int e) const { return (w[e >> 6] >> (e & 63)) & 1; }
+    LegSet operator^(const LegSet &o) const { LegSet r; for (int i = 0; i < 4; ++i) r.w[i] = w[i] ^ o.w[i]; return r; }
+    LegSet operator|(const LegSet &o) const { LegSet r; for (int i = 0; i < 4; ++i) r.w[i] = w[i] | o.w[i]; return r; }
+};
+
+struct TreeCtx {
+    std::vector<LegSet> site;   // bonds of each site (dimension > 1)
+    std::vector<double> lg;     // log2 dimension per edge
+    double size(const LegSet &s) const {
+        double x = 0;
+        for (int i = 0; i < 4; ++i)
+            for (uint64_t m = s.w[i]; m; m &= m - 1) x += lg[64 * i + __builtin_ctzll(m)];
+        return x;
+    }
+};
+
+TreeCtx tree_ctx(const Circuit &c, const std::vector<double> &d) {
+    if (c.g.edges.size() > 256) fail(TNS_E_UNSUPPORTED, "more than 256 bonds");
+    TreeCtx t;
+    t.site.assign(c.n, LegSet{});
+    t.lg.assign(256, 0.0);
+    for (size_t e = 0; e < c.g.edges.size(); ++e) {
+        if (!(d[e] > 1.0)) continue;
+        t.lg[e] = std::log2(d[e]);
+        t.site[c.g.edges[e].first].flip((int)e);
+        if (c.g.edges[e].second < c.n) t.site[c.g.edges[e].second].flip((int)e);
+    }
+    return t;
+}
+
+struct TreeEval {
+    double score = 0;        // sum of M K N
+    double peak = 0;         // log2 of the largest main-path operand or result
+    double branch_peak = 0;  // log2 of the largest branch tensor
+};
+
+// windows: disjoint [a, b) ranges of positions, sorted by a, a >= 1
+TreeEval tree_eval(const TreeCtx &t, const std::vector<int> &order,
+                   const std::vector<std::pair<int, int>> &windows) {
+    const int n = (int)order.size();
+    std::vector<int> win(n, -1);
+    for (size_t w = 0; w < windows.size(); ++w)
+        for (int i = windows[w].first; i < windows[w].second; ++i) win[i] = (int)w;
+    TreeEval ev;
+    auto branch = [&](int w) {
+        LegSet B = t.site[order[windows[w].first]];
+        ev.branch_peak = std::max(ev.branch_peak, t.size(B));
+        for (int i = windows[w].first + 1; i < windows[w].second; ++i) {
+            const LegSet &S = t.site[order[i]];
+            ev.score += std::exp2(t.size(B | S));
+            B = B ^ S;
+            ev.branch_peak = std::max(ev.branch_peak, t.size(B));
+        }
+        return B;
+    };
+    std::vector<int> by_end(windows.size());
+    std::iota(by_end.begin(), by_end.end(), 0);
+    std::stable_sort(by_end.begin(), by_end.end(),
+                     [&](int x, int y) { return windows[x].second < windows[y].second; });
+    size_t next = 0;
+    LegSet T;
+    bool started = false;
+    auto absorb = [&](const LegSet &X) {
+        ev.score += std::exp2(t.size(T | X));
+        T = T ^ X;
+        ev.peak = std::max(ev.peak, t.size(T));
+    };
+    for (int i = 0; i < n; ++i) {
+        if (win[i] >= 0) continue;
+        while (started && next < by_end.size() && windows[by_end[next]].second <= i) absorb(branch(by_end[next++]));
+        if (!started) {
+            T = t.site[order[i]];
+            ev.peak = t.size(T);
+            started = true;
+        } else {
+            ev.peak = std::max(ev.peak, t.size(T));
+            absorb(t.site[order[i]]);
+        }
+    }
+    while (next < by_end.size()) absorb(branch(by_end[next++]));
+    return ev;
+}
+
+}  // namespace
+
+// Greedy choice of branch windows for a fixed order: repeatedly add the
+// window (length 2..16, disjoint from those chosen) that lowers the summed
+// cost most while every main-path tensor stays within log2_limit and every
+// branch tensor within log2_branch_limit; stops when no window helps.
+std::vector<std::pair<int, int>> choose_branches(const Circuit &c, const std::vector<double> &d,
+                                                 const std::vector<int> &order, double log2_limit,
+                                                 double log2_branch_limit, double *score_out) {
+    const TreeCtx t = tree_ctx(c, d);
+    const int n = (int)order.size();
+    std::vector<std::pair<int, int>> cur;
+    double best = tree_eval(t, order, cur).score;
+    for (;;) {
+        std::vector<char> used(n, 0);
+        for (auto &w : cur)
+            for (int i = w.first; i < w.second; ++i) used[i] = 1;
+        std::pair<int, int> pick{-1, -1};
+        double pick_score = best;
+        for (int a = 1; a + 1 < n; ++a) {
+            if (used[a]) continue;
+            for (int b = a + 2; b <= std::min(n, a + 16); ++b) {
+                if (used[b - 1]) break;
+                auto trial = cur;
+                trial.push_back({a, b});
+                std::sort(trial.begin(), trial.end());
+                const TreeEval ev = tree_eval(t, order, trial);
+                if (ev.peak > log2_limit + 1e-9 || ev.branch_peak > log2_branch_limit + 1e-9) continue;
+                if (ev.score < pick_score * (1 - 1e-9)) {
+                    pick_score = ev.score;
+                    pick = {a, b};
+                }
+            }
+        }
+        if (pick.first < 0) break;
+        cur.push_back(pick);
+        std::sort(cur.begin(), cur.end());
+        best = pick_score;
+    }
+    if (score_out) *score_out = best;
+    return cur;
+}
+
 static void compile_steps(Plan &p) {
     const Circuit &c = p.circ;
     const int n = c.n;
     const auto &order = p.path.order;
-    std::vector<int64_t> d(c.g.edges.size());
-    std::vector<char> is_cut(c.g.edges.size(), 0);
+    const int n_edges = (int)c.g.edges.size();
+    std::vector<int64_t> d(n_edges);
+    std::vector<char> is_cut(n_edges, 0);
     for (int e : p.cuts) is_cut[e] = 1;
-    for (size_t e = 0; e < d.size(); ++e) d[e] = is_cut[e] ? 1 : p.bond_overlap[e];
-    std::vector<int> pos(n + 1);
-    for (int m = 0; m < n; ++m) pos[order[m]] = m;
-    pos[n] = std::numeric_limits<int>::max();   // open legs are never consumed
-    auto consumed = [&](int e) { return std::max(pos[c.g.edges[e].first], pos[c.g.edges[e].second]); };
+    for (int e = 0; e < n_edges; ++e) d[e] = is_cut[e] ? 1 : p.bond_overlap[e];
     auto logical_legs = [&](int q) {
         std::vector<int> v;
         for (int e : c.g.legs[q])
             if (d[e] > 1) v.push_back(e);
         return v;
     };
+
+    // The contraction program in execution order: each chain (0 = the main
+    // path, w + 1 = branch w) starts from one site tensor and absorbs sites;
+    // the main path absorbs branch w's tensor just before it reaches the end
+    // of the branch's window.
+    struct Op { int chain, kind, id; };   // kind 0: start at site id, 1: absorb site id, 2: absorb branch id
+    std::vector<Op> ops;
+    {
+        const auto &W = p.branches;
+        std::vector<int> win(n, -1), by_end(W.size());
+        for (size_t w = 0; w < W.size(); ++w) {
+            if (W[w].first < 1 || W[w].second > n || W[w].second - W[w].first < 2)
+                fail(TNS_E_BAD_PATH, "internal: bad branch window");
+            for (int i = W[w].first; i < W[w].second; ++i) {
+                if (win[i] >= 0) fail(TNS_E_BAD_PATH, "internal: overlapping branch windows");
+                win[i] = (int)w;
+            }
+        }
+        std::iota(by_end.begin(), by_end.end(), 0);
+        std::stable_sort(by_end.begin(), by_end.end(), [&](int x, int y) { return W[x].second < W[y].second; });
+        size_t next = 0;
+        bool started = false;
+        auto branch = [&](int w) {
+            ops.push_back({w + 1, 0, order[W[w].first]});
+            for (int i = W[w].first + 1; i < W[w].second; ++i) ops.push_back({w + 1, 1, order[i]});
+            ops.push_back({0, 2, w});
+        };
+        for (int i = 0; i < n; ++i) {
+            if (win[i] >= 0) continue;
+            while (started && next < by_end.size() && W[by_end[next]].second <= i) branch(by_end[next++]);
+            ops.push_back({0, started ? 1 : 0, order[i]});
+            started = true;
+        }
+        while (next < by_end.size()) branch(by_end[next++]);
+    }
+    // the op at which each bond is contracted (open legs: never)
+    std::vector<int> cons(n_edges, std::numeric_limits<int>::max());
+    {
+        std::vector<std::vector<char>> held(p.branches.size() + 1, std::vector<char>(n_edges, 0));
+        for (int k = 0; k < (int)ops.size(); ++k) {
+            const Op &o = ops[k];
+            std::vector<char> x(n_edges, 0);
+            if (o.kind == 2) x = held[o.id + 1];
+            else for (int e : logical_legs(o.id)) x[e] = 1;
+            std::vector<char> &t = held[o.chain];
+            if (o.kind == 0) { t = x; continue; }
+            for (int e = 0; e < n_edges; ++e) {
+                if (t[e] && x[e]) cons[e] = k;
+                t[e] ^= x[e];
+            }
+        }
+    }
+    auto consumed = [&](int e) { return cons[e]; };
     // physical stride of bond e inside site q's overlap tensor (bonds in edge-id order)
     auto site_stride = [&](int q, int e) {
         int64_t st = 1;
@@ -717,56 +911,76 @@ static void compile_steps(Plan &p) {
     p.steps.clear();
     const int elem = (p.precision == TNS_C128) ? 16 : 8;
     p.peak_elems = 0;
+    p.branch_peak_elems = 0;
     p.max_b_elems = 0;
     p.flops_per_amp = p.gemm_bytes_per_amp = p.permute_bytes_per_amp = 0;
     p.path_score = 0;
 
-    // step 0: the starting tensor
-    Step s0;
-    s0.site = order[0];
-    s0.n_legs = logical_legs(order[0]);
-    by_consumption_desc(s0.n_legs);
-    {
-        std::vector<int64_t> sz, st;
-        for (int e : s0.n_legs) { sz.push_back(d[e]); st.push_back(site_stride(order[0], e)); }
-        s0.bgather = compact(sz, st);
-    }
-    s0.N = prod(s0.n_legs);
-    s0.out_elems = s0.N;
-    p.peak_elems = s0.N;
-    std::vector<int> T = s0.n_legs;
-    p.steps.push_back(s0);
-
-    for (int m = 1; m < n; ++m) {
-        const int j = order[m];
+    std::vector<std::vector<int>> T(p.branches.size() + 1);   // legs of each chain's tensor, storage order
+    std::vector<int> last(p.branches.size() + 1, -1);          // step that produced it
+    for (int k = 0; k < (int)ops.size(); ++k) {
+        const Op &o = ops[k];
         Step s;
-        s.site = j;
-        s.t_legs = T;
-        std::vector<int> lj = logical_legs(j);
+        s.chain = o.chain;
+        int64_t &peak = o.chain == 0 ? p.peak_elems : p.branch_peak_elems;
+        if (o.kind == 0) {
+            // the starting tensor of a chain, gathered from its site
+            s.start = true;
+            s.site = o.id;
+            s.n_legs = logical_legs(o.id);
+            by_consumption_desc(s.n_legs);
+            std::vector<int64_t> sz, st;
+            for (int e : s.n_legs) { sz.push_back(d[e]); st.push_back(site_stride(o.id, e)); }
+            s.bgather = compact(sz, st);
+            s.N = prod(s.n_legs);
+            s.out_elems = s.N;
+            peak = std::max(peak, s.N);
+            T[o.chain] = s.n_legs;
+            last[o.chain] = (int)p.steps.size();
+            p.steps.push_back(s);
+            continue;
+        }
+        // the absorbed operand: a site tensor, or a branch's tensor (row-major
+        // over its legs in storage order)
+        std::vector<int> lj;
+        std::vector<int64_t> xstride(n_edges, 0);
+        if (o.kind == 1) {
+            s.site = o.id;
+            lj = logical_legs(o.id);
+            for (int e : lj) xstride[e] = site_stride(o.id, e);
+        } else {
+            s.branch = o.id;
+            lj = T[o.id + 1];
+            int64_t st = 1;
+            for (int i = (int)lj.size() - 1; i >= 0; --i) { xstride[lj[i]] = st; st *= d[lj[i]]; }
+        }
+        s.prev = last[o.chain];
+        std::vector<int> &Tc = T[o.chain];
+        s.t_legs = Tc;
         std::vector<int> S, Mv;
-        for (int e : T)
+        for (int e : Tc)
             if (std::find(lj.begin(), lj.end(), e) != lj.end()) S.push_back(e); else Mv.push_back(e);
         // Are the shared legs already the trailing legs of T?
         bool trailing = true;
         for (size_t i = 0; i < S.size(); ++i)
-            if (T[T.size() - S.size() + i] != S[i]) trailing = false;
+            if (Tc[Tc.size() - S.size() + i] != S[i]) trailing = false;
         if (!trailing) {
             s.permute = true;
             by_consumption_desc(Mv);
             std::vector<int> neworder = Mv;
             neworder.insert(neworder.end(), S.begin(), S.end());
             // source strides of T (row-major over T)
-            std::vector<int64_t> tstride(T.size());
+            std::vector<int64_t> tstride(Tc.size());
             int64_t st = 1;
-            for (int i = (int)T.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[T[i]]; }
+            for (int i = (int)Tc.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[Tc[i]]; }
             std::vector<int64_t> sz, sst;
             for (int e : neworder) {
-                int i = (int)(std::find(T.begin(), T.end(), e) - T.begin());
+                int i = (int)(std::find(Tc.begin(), Tc.end(), e) - Tc.begin());
                 sz.push_back(d[e]);
                 sst.push_back(tstride[i]);
             }
             s.perm = compact(sz, sst);
-            p.permute_bytes_per_amp += 2.0 * elem * (double)prod(T);
+            p.permute_bytes_per_amp += 2.0 * elem * (double)prod(Tc);
         }
         s.m_legs = Mv;
         s.k_legs = S;
@@ -779,16 +993,17 @@ static void compile_steps(Plan &p) {
         {
             // B[n][k]: new legs (slow) then shared legs in T's order (fast)
             std::vector<int64_t> sz, st;
-            for (int e : s.n_legs) { sz.push_back(d[e]); st.push_back(site_stride(j, e)); }
-            for (int e : S) { sz.push_back(d[e]); st.push_back(site_stride(j, e)); }
+            for (int e : s.n_legs) { sz.push_back(d[e]); st.push_back(xstride[e]); }
+            for (int e : S) { sz.push_back(d[e]); st.push_back(xstride[e]); }
             s.bgather = compact(sz, st);
         }
         s.out_elems = s.M * s.N;
-        const bool last = (m == n - 1);
-        if (last && c.n_open == 0) {
+        const bool final_op = (k + 1 == (int)ops.size());
+        if (final_op && o.chain != 0) fail(TNS_E_BAD_PATH, "internal: the program does not end on the main path");
+        if (final_op && c.n_open == 0) {
             if (s.M != 1 || s.N != 1) fail(TNS_E_BAD_PATH, "internal: final step is not a scalar");
             s.kernel = 2;
-        } else if (last && s.M * s.N != ((int64_t)1 << c.n_open)) {
+        } else if (final_op && s.M * s.N != ((int64_t)1 << c.n_open)) {
             fail(TNS_E_BAD_PATH, "internal: final tensor does not hold the open legs");
         } else if (s.K >= 16 && s.N >= 16 && s.M >= 16 && s.K % 2 == 0) {
             // complex64 wide steps: three real products instead of four
@@ -796,21 +1011,26 @@ static void compile_steps(Plan &p) {
         } else {
             s.kernel = 1;
         }
-        T = Mv;
-        T.insert(T.end(), s.n_legs.begin(), s.n_legs.end());
-        p.peak_elems = std::max(p.peak_elems, std::max(s.out_elems, s.M * s.K));
+        Tc = Mv;
+        Tc.insert(Tc.end(), s.n_legs.begin(), s.n_legs.end());
+        peak = std::max(peak, std::max(s.out_elems, s.M * s.K));
         p.max_b_elems = std::max(p.max_b_elems, s.K * s.N);
         const double mkn = (double)s.M * (double)s.K * (double)s.N;
         p.path_score += mkn;
         p.flops_per_amp += 8.0 * mkn;
         p.gemm_bytes_per_amp += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
+        last[o.chain] = (int)p.steps.size();
         p.steps.push_back(s);
     }
+    const std::vector<int> &Tfinal = T[0];
     // a boundary permute after a GEMM step (either form), or after a small
-    // step that the row-tiled kernel takes, goes into that step's store
-    for (size_t m = 2; m < p.steps.size(); ++m) {
-        Step &s = p.steps[m], &prev = p.steps[m - 1];
-        if (!s.permute) continue;
+    // step that the row-tiled kernel takes, goes into that step's store (the
+    // step of the same chain that produced the permuted tensor)
+    for (size_t m = 0; m < p.steps.size(); ++m) {
+        Step &s = p.steps[m];
+        if (!s.permute || s.prev < 0) continue;
+        Step &prev = p.steps[s.prev];
+        if (prev.start) continue;
         if (prev.kernel != 0 && prev.kernel != 3 &&
             !(prev.kernel == 1 && small_rows_fits(prev.M, prev.K, prev.N, elem)))
             continue;
@@ -823,14 +1043,14 @@ static void compile_steps(Plan &p) {
     // open legs of the last tensor -> output order (first open qubit most significant)
     p.out_per_unit = (int64_t)1 << c.n_open;
     if (c.n_open > 0) {
-        std::vector<int64_t> tstride(T.size());
+        std::vector<int64_t> tstride(Tfinal.size());
         int64_t st = 1;
-        for (int i = (int)T.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[T[i]]; }
+        for (int i = (int)Tfinal.size() - 1; i >= 0; --i) { tstride[i] = st; st *= d[Tfinal[i]]; }
         std::vector<int64_t> sz, sst;
         for (int k = 0; k < c.n_open; ++k) {
             const int e = c.n_real_edges + k;
-            const int i = (int)(std::find(T.begin(), T.end(), e) - T.begin());
-            if (i >= (int)T.size()) fail(TNS_E_BAD_PATH, "internal: open leg missing from the last tensor");
+            const int i = (int)(std::find(Tfinal.begin(), Tfinal.end(), e) - Tfinal.begin());
+            if (i >= (int)Tfinal.size()) fail(TNS_E_BAD_PATH, "internal: open leg missing from the last tensor");
             sz.push_back(2);
             sst.push_back(tstride[i]);
         }
@@ -1217,6 +1437,22 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
             p.site_elems[q] *= p.bond_overlap[e];
         }
     choose_cuts_and_path(p);
+    // several main paths: side branches of the linear order where they lower
+    // the summed cost, within the intermediate limit (or the linear path's
+    // own peak, when given cuts leave it above the limit)
+    p.branches.clear();
+    {
+        const std::vector<double> dc = dims_with_cuts(p, p.cuts);
+        double lpeak = 0;
+        p.linear_score = path_score(c.n, c.g.edges, dc, p.path.order, &lpeak, nullptr);
+        if (opts.path_branches) {
+            const double limit = (double)(opts.max_intermediate_elems ? opts.max_intermediate_elems
+                                                                       : (1ULL << 32));
+            const double lim = std::max(std::log2(limit), std::log2(lpeak));
+            p.branches = choose_branches(c, dc, p.path.order, lim,
+                                         std::min(lim, std::log2((double)kBranchPeakElems)), nullptr);
+        }
+    }
     compile_steps(p);
 
     // scratch for the SVD's V' of the bra side (per bitstring)
@@ -1247,7 +1483,15 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
 
     p.info_path = p.path.order;
     p.info_m.clear(); p.info_k.clear(); p.info_n.clear(); p.info_kernel.clear(); p.info_permute.clear();
-    for (size_t i = 1; i < p.steps.size(); ++i) {
+    p.info_chain.clear();
+    p.info_branch_windows.clear();
+    for (auto &w : p.branches) {
+        p.info_branch_windows.push_back(w.first);
+        p.info_branch_windows.push_back(w.second);
+    }
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        if (p.steps[i].start) continue;
+        p.info_chain.push_back(p.steps[i].chain);
         p.info_m.push_back(p.steps[i].M);
         p.info_k.push_back(p.steps[i].K);
         p.info_n.push_back(p.steps[i].N);
@@ -1256,8 +1500,12 @@ void plan_host(const Circuit &c, const tns_plan_opts &opts, Plan &p) {
     }
     const int elem = p.precision == TNS_C128 ? 16 : 8;
     // one unit: two boundary buffers, the B operand (embedded form is 2x) and the partial
-    p.unit_stride = (p.peak_elems + 31) / 32 * 32;
-    p.bytes_per_unit = 2 * p.unit_stride * elem + 2 * p.max_b_elems * elem + 16;
+    // (a branch's tensors also pass through the main buffer the main path is
+    // not using, so it holds the larger of the two peaks)
+    p.unit_stride = (std::max(p.peak_elems, p.branch_peak_elems) + 31) / 32 * 32;
+    // and, with branches, the branch buffer
+    p.branch_stride = p.branches.empty() ? 0 : (p.branch_peak_elems + 31) / 32 * 32;
+    p.bytes_per_unit = (2 * p.unit_stride + p.branch_stride) * elem + 2 * p.max_b_elems * elem + 16;
     int64_t sites = 0, bra = 0;
     for (int q = 0; q < c.n; ++q) {
         sites += p.site_elems[q];

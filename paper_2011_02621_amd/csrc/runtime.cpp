@@ -242,7 +242,7 @@ int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget) {
     return std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
 }
 
-enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_COUNT };
+enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_TZ, S_COUNT };
 
 uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t budget) {
     // mirrors the slot sizes run_amplitudes takes from a fresh workspace
@@ -267,6 +267,7 @@ uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t b
     const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max<int64_t>(p.unit_stride, 1));
     G = std::max<int64_t>(1, std::min<int64_t>(std::min(G, fill), units));
     used += 2 * slot(G * p.unit_stride * elem) + slot(G * p.max_b_elems * 2 * elem);
+    if (p.branch_stride) used += slot(G * p.branch_stride * elem);
     return used;
 }
 
@@ -342,6 +343,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         char *X = (char *)ws.get(ctx, S_TX, (size_t)G * peak * elem, stream);
         char *Y = (char *)ws.get(ctx, S_TY, (size_t)G * peak * elem, stream);
         char *Bb = (char *)ws.get(ctx, S_B, (size_t)G * p.max_b_elems * 2 * elem, stream);
+        char *Z = p.branch_stride ? (char *)ws.get(ctx, S_TZ, (size_t)G * p.branch_stride * elem, stream) : nullptr;
         if (!bits_dev_in)
             hip_check(hipMemcpyAsync(bits_dev, bits_host + b0 * c.n, (size_t)nb * c.n,
                                      hipMemcpyHostToDevice, (hipStream_t)stream), "bits upload");
@@ -406,61 +408,83 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         for (int64_t ug0 = 0; ug0 < units; ug0 += G) {
             if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
             const int64_t g = std::min(G, units - ug0);
-            const Step &s0 = p.steps[0];
-            launch::gather_site(site_ptr[s0.site], X, g, ug0, n_sl, slice_begin, p.site_elems[s0.site],
-                                p.slice_map[s0.site],
-                                peak, s0.bgather, elem, stream);
-            char *cur = X;
-            st.launches += 1;
-            for (size_t m = 1; m < p.steps.size(); ++m) {
+            // Boundary buffers: X and Y hold the main path's tensor (ping-pong);
+            // a branch's tensors alternate between Z and whichever of X / Y
+            // the main path is not using.  An absorbed branch tensor is first
+            // copied into the B operand, so its buffer is free again before
+            // the step's permute and GEMM write.
+            struct Buf { char *p; int64_t us; };
+            const Buf bx{X, peak}, by{Y, peak}, bz{Z, p.branch_stride};
+            Buf cur_main{nullptr, 0}, cur_br{nullptr, 0};
+            auto free_main = [&]() { return cur_main.p == X ? by : bx; };
+            for (size_t m = 0; m < p.steps.size(); ++m) {
                 const Step &s = p.steps[m];
-                char *src = cur;
-                char *other = (cur == X) ? Y : X;
+                const bool main = s.chain == 0;
+                if (s.start) {
+                    const Buf to = main ? bx : bz;
+                    launch::gather_site(site_ptr[s.site], to.p, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
+                                        p.slice_map[s.site], to.us, s.bgather, elem, stream);
+                    (main ? cur_main : cur_br) = to;
+                    st.launches += 1;
+                    continue;
+                }
+                // B[n][k] from the absorbed tensor: the real-embedded GEMM takes its
+                // real embedding, the three-multiplication GEMM and the small kernels
+                // the plain complex matrix
+                if (s.branch < 0)
+                    launch::build_b(site_ptr[s.site], Bb, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
+                                    p.slice_map[s.site], s.bgather, s.K, s.N, c64 ? 1 : 0,
+                                    s.kernel == 0 ? 1 : 0, stream);
+                else
+                    launch::build_b(cur_br.p, Bb, g, 0, 1, 0, cur_br.us, SliceMap{}, s.bgather, s.K, s.N,
+                                    c64 ? 1 : 0, s.kernel == 0 ? 1 : 0, stream);
+                const Buf cur = main ? cur_main : cur_br;
+                auto other_of = [&](const Buf &b) {
+                    if (main) return b.p == X ? by : bx;
+                    return b.p == Z ? free_main() : bz;
+                };
+                Buf src = cur;
                 if (s.permute && !s.permute_fused) {
                     int64_t te = 1;
                     for (int a = 0; a < s.perm.n; ++a) te *= s.perm.size[a];
+                    const Buf o = other_of(cur);
                     ev_begin(1, 0, 2.0 * elem * te * g);
-                    launch::gather(cur, other, g, peak, peak, s.perm, elem, stream);
+                    launch::gather(cur.p, o.p, g, cur.us, o.us, s.perm, elem, stream);
                     ev_end();
-                    src = other;
+                    src = o;
                     st.launches += 1;
                 }
-                char *dst = (src == X) ? Y : X;
-                // the real-embedded GEMM takes B as its real embedding, the
-                // three-multiplication GEMM and the small kernels as plain complex
-                launch::build_b(site_ptr[s.site], Bb, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
-                                p.slice_map[s.site],
-                                s.bgather, s.K, s.N, c64 ? 1 : 0, s.kernel == 0 ? 1 : 0, stream);
+                const Buf dst = other_of(src);
                 const double mkn = (double)s.M * s.K * s.N * g;
-                const double by = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
+                const double bytes = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
                 const bool is_gemm = s.kernel == 0 || s.kernel == 3;
                 // real flops the MFMA instructions execute: 8 M K N for the real
                 // embedding, 6 M K N for the three-multiplication form, times the
                 // number of products of a split-BF16 form
                 const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
                                     : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
-                ev_begin(s.kernel == 3 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, by,
+                ev_begin(s.kernel == 3 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
                          (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
-                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, p.precision, stream,
-                                 s.store_fused ? &p.scatter[m] : nullptr);
+                    launch::gemm(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us, p.precision,
+                                 stream, s.store_fused ? &p.scatter[m] : nullptr);
                 else if (s.kernel == 3)
-                    launch::gemm(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak, 4, stream,
+                    launch::gemm(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us, 4, stream,
                                  s.store_fused ? &p.scatter[m] : nullptr);
                 else if (s.kernel == 1)
-                    launch::small_contract(src, Bb, dst, g, s.M, s.K, s.N, peak, s.K * s.N, peak,
+                    launch::small_contract(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us,
                                            c64 ? 1 : 0, stream, s.store_fused ? &p.scatter[m] : nullptr);
                 else
-                    launch::final_dot(src, Bb, partial + 2 * ug0, g, s.K, peak, s.K, c64 ? 1 : 0, stream);
+                    launch::final_dot(src.p, Bb, partial + 2 * ug0, g, s.K, src.us, s.K, c64 ? 1 : 0, stream);
                 ev_end();
                 if (m + 1 == p.steps.size() && s.kernel != 2) {
                     // open legs: the last tensor holds this unit's 2^open values
-                    launch::finalize(dst, partial + 2 * ug0 * opu, g, peak, opu, p.final_perm,
+                    launch::finalize(dst.p, partial + 2 * ug0 * opu, g, dst.us, opu, p.final_perm,
                                      c64 ? 1 : 0, stream);
                     st.launches += 1;
                 }
                 st.launches += 2;
-                cur = dst;
+                (main ? cur_main : cur_br) = dst;
             }
         }
         launch::slice_sum(partial, amps_dev + 2 * b0 * opu, nb, n_sl, opu, stream);

@@ -134,10 +134,38 @@ def test_plan_info_consistency(ctx):
     flops = 8 * np.sum(i.step_m.astype(float) * i.step_k * i.step_n) * i.n_slices
     assert flops == pytest.approx(i.flops_per_amp)
     assert i.step_m[-1] == 1 and i.step_n[-1] == 1 and i.step_kernel[-1] == 2
-    # the reported score is the oracle's score of the same order
+    # the reported scores are the oracle's: the order as one linear path, and
+    # the plan with its side branches
     dims = [float(d) for d in i.bond_overlap]
-    s, peak = paths.score(i.path.tolist(), c.n, c.edges, dims)
-    assert s == pytest.approx(i.path_score) and peak == i.peak_elems
+    s, _ = paths.score(i.path.tolist(), c.n, c.edges, dims)
+    assert s == pytest.approx(i.linear_score)
+    windows = [tuple(w) for w in i.branch_windows.tolist()]
+    ts, peak, bpeak = paths.tree_score(i.path.tolist(), windows, c.n, c.edges, dims)
+    assert ts == pytest.approx(i.path_score) and peak == i.peak_elems
+    assert len(windows) > 0 and i.path_score < i.linear_score
+    assert set(i.step_chain.tolist()) == set(range(len(windows) + 1))
+
+
+def test_branches_off_is_the_linear_path(ctx):
+    c, _ = config("grid5x5_d10")
+    i = ctx.plan(c, precision="c64", branches=False).info()
+    assert len(i.branch_windows) == 0 and i.path_score == pytest.approx(i.linear_score)
+    assert set(i.step_chain.tolist()) == {0}
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_branch_plans_within_the_tree_optimum(ctx, seed):
+    # 3x3 grids: the plan's summed cost, with whatever branches it chose, is
+    # the oracle's cost of that plan, no worse than its own linear path, and
+    # no better than the best contraction tree (exhaustive, oracle)
+    c = random_circuit(grid(3, 3), 5, seed)
+    i = ctx.plan(c, precision="c64").info()
+    dims = [float(d) for d in i.bond_overlap]
+    windows = [tuple(w) for w in i.branch_windows.tolist()]
+    ts, peak, _ = paths.tree_score(i.path.tolist(), windows, c.n, c.edges, dims)
+    assert ts == pytest.approx(i.path_score) and peak == i.peak_elems
+    assert i.path_score <= i.linear_score * (1 + 1e-12)
+    assert paths.tree_optimum(c.n, c.edges, dims) <= i.path_score * (1 + 1e-12)
 
 
 def _small_rows_fits(m, k, n, csize):
@@ -166,10 +194,14 @@ def test_permutes_fused_into_stores(ctx, workload):
                 if k[t] in (0, 3) and kk[t] % 2 == 0 and kk[t] >= 128 and n[t] >= 64 and m[t] >= 64]
         assert all(k[t] == (3 if prec == "c64" else 0) for t in wide)
         assert (sp == 2).sum() > 0
+        # the producer of step t's boundary tensor: the previous step of the
+        # same chain (main path or branch), none for a chain's first step
+        ch = np.asarray(i.step_chain)
+        prod = [max([u for u in range(t) if ch[u] == ch[t]], default=-1) for t in range(len(k))]
         for t in np.nonzero(sp == 2)[0]:
-            assert t >= 1 and fusable[t - 1]
+            assert prod[t] >= 0 and fusable[prod[t]]
         for t in np.nonzero(sp == 1)[0]:
-            assert t == 0 or not fusable[t - 1]
+            assert prod[t] < 0 or not fusable[prod[t]]
         if workload == "diag53_d12":
             # the large permutes there follow small steps
             assert any(sp[t] == 2 and k[t - 1] == 1 for t in range(1, len(k)))

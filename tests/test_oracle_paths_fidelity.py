@@ -47,6 +47,43 @@ def test_brute_force_equals_subset_dp(seed):
     assert paths.brute_force(n, edges, dims)[0] == paths.subset_dp(n, edges, dims)
 
 
+def test_bridge_by_hand():
+    # two heavy pairs joined by a thin bond: A -(8)- B -(2)- C -(8)- D.
+    # Linear A,B,C,D: Cost(A,B) = 8*2 = 16, Cost({A,B},C) = 2*8 = 16,
+    # Cost({A,B,C},D) = 8 -> 40, and no linear order does better.  With C,D
+    # as a side branch (window of positions 2..3): the branch costs
+    # Cost(C,D) = 2*8 = 16, the main path Cost(A,B) = 16, and absorbing the
+    # branch's tensor (only the thin bond left) costs 2 -> 34, which is also
+    # the best of every contraction tree.
+    edges, dims = [(0, 1), (1, 2), (2, 3)], [8, 2, 8]
+    assert paths.score([0, 1, 2, 3], 4, edges, dims)[0] == 40
+    assert paths.subset_dp(4, edges, dims) == 40
+    s, peak, bpeak = paths.tree_score([0, 1, 2, 3], [(2, 4)], 4, edges, dims)
+    assert (s, peak, bpeak) == (34, 8, 16)
+    assert paths.tree_optimum(4, edges, dims) == 34
+
+
+def test_tree_optimum_by_hand():
+    # the 3-site chain above: pairing (1,2) first costs a*b = 6, then the
+    # remaining leg a = 2 -> 8, the same as the best linear order
+    assert paths.tree_optimum(3, [(0, 1), (1, 2)], [2, 3]) == 8
+    # triangle: every tree pairs two sites first (64) and then meets the
+    # third site through its two legs; the cheapest pair leaves 2 * 4
+    assert paths.tree_optimum(3, [(0, 1), (1, 2), (0, 2)], [2, 4, 8]) == 64 + 8
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tree_score_without_windows_is_linear(seed):
+    rng = np.random.default_rng(seed)
+    g = grid(3, 3)
+    dims = [int(2 ** rng.integers(1, 4)) for _ in g.edges]
+    order = [int(x) for x in rng.permutation(g.n)]
+    s, peak = paths.score(order, g.n, g.edges, dims)
+    assert paths.tree_score(order, [], g.n, g.edges, dims)[:2] == (s, peak)
+    # a tree contraction can only do as well as or better than linear paths
+    assert paths.tree_optimum(g.n, g.edges, dims) <= paths.subset_dp(g.n, g.edges, dims)
+
+
 def test_intermediate_size_tracks_open_legs():
     g = grid(2, 3)
     dims = [2] * len(g.edges)
