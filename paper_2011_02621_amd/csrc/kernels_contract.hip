@@ -1001,6 +1001,70 @@ __global__ __launch_bounds__(256) void k_small_rows(const R *__restrict__ A, con
     }
 }
 
+// Fixed small K x N (8 x 8: the steps that absorb a site through two bonds
+// of dimension 8 on either side), one row per thread: a block stages 256
+// consecutive rows of A (one unit, contiguous) in LDS with 16-byte loads,
+// every thread keeps its row in registers, reads B^T (broadcast, all lanes
+// the same address) and writes its N outputs -- row-major, or through the
+// fused-store tables, where consecutive rows (lanes) are contiguous in the
+// target when sc.mfast.  Same arithmetic and order as k_small_rows.
+template <typename R, int KK, int NN, bool SCAT>
+__global__ __launch_bounds__(256) void k_small_fixed(const R *__restrict__ A, const R *__restrict__ Bt,
+                                                     R *__restrict__ C, int64_t M, int64_t sA, int64_t sB,
+                                                     int64_t sC, ScatterStore sc) {
+    using C2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    constexpr int LD = KK + 1;
+    __shared__ C2 As[256 * LD];
+    __shared__ C2 Bs[NN * KK];
+    const int64_t u = blockIdx.y;
+    const int64_t m0 = (int64_t)blockIdx.x * 256;
+    const int rows = (int)(M - m0 < 256 ? M - m0 : 256);
+    const int tid = threadIdx.x;
+    const C2 *a = reinterpret_cast<const C2 *>(A) + u * sA + m0 * KK;
+    const C2 *b = reinterpret_cast<const C2 *>(Bt) + u * sB;
+    for (int i = tid; i < NN * KK; i += 256) Bs[i] = b[i];
+    if constexpr (sizeof(R) == 4 && KK % 2 == 0) {
+        // two complex64 values per 16-byte load (the chunk starts 16-byte aligned)
+        const float4 *a4 = reinterpret_cast<const float4 *>(a);
+        for (int i = tid; i < rows * KK / 2; i += 256) {
+            const float4 v = a4[i];
+            const int r = (2 * i) / KK, k = 2 * i - r * KK;
+            As[r * LD + k] = C2{v.x, v.y};
+            As[r * LD + k + 1] = C2{v.z, v.w};
+        }
+    } else {
+        for (int i = tid; i < rows * KK; i += 256) {
+            const int r = i / KK;
+            As[r * LD + (i - r * KK)] = a[i];
+        }
+    }
+    __syncthreads();
+    if (tid >= rows) return;
+    C2 x[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) x[k] = As[tid * LD + k];
+    const int64_t row = m0 + tid;
+    C2 *c = reinterpret_cast<C2 *>(C) + u * sC;
+    int64_t base;
+    if constexpr (SCAT) base = sc.fa[row >> sc.shift] + sc.fb[row & (((int64_t)1 << sc.shift) - 1)];
+    else base = row * NN;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int k = 0; k < KK; ++k) {
+            const C2 y = Bs[n * KK + k];
+            re += x[k].x * y.x - x[k].y * y.y;
+            im += x[k].x * y.y + x[k].y * y.x;
+        }
+        C2 v;
+        v.x = re;
+        v.y = im;
+        if constexpr (SCAT) c[base + sc.fg[n]] = v;
+        else c[base + n] = v;
+    }
+}
+
 // the general case: one thread per output element
 
 template <typename R, typename Acc>
@@ -1032,29 +1096,33 @@ __global__ __launch_bounds__(256) void k_final_dot(const R *__restrict__ A,
                                                     const R *__restrict__ Bt,
                                                     double *__restrict__ partial, int64_t K,
                                                     int64_t sA, int64_t sB) {
-    __shared__ double sre[256], sim[256];
+    using C2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    __shared__ double wre[4], wim[4];
     const int64_t u = blockIdx.x;
-    const R *a = A + 2 * u * sA;
-    const R *b = Bt + 2 * u * sB;
+    const C2 *a = reinterpret_cast<const C2 *>(A) + u * sA;
+    const C2 *b = reinterpret_cast<const C2 *>(Bt) + u * sB;
     double re = 0, im = 0;
     for (int64_t k = threadIdx.x; k < K; k += 256) {
-        const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+        const C2 x = a[k], y = b[k];
+        const double ar = x.x, ai = x.y, br = y.x, bi = y.y;
         re += ar * br - ai * bi;
         im += ar * bi + ai * br;
     }
-    sre[threadIdx.x] = re;
-    sim[threadIdx.x] = im;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sre[threadIdx.x] += sre[threadIdx.x + w];
-            sim[threadIdx.x] += sim[threadIdx.x + w];
-        }
-        __syncthreads();
+    // wave64 butterfly: every lane ends with its wave's sum (fixed order)
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        re += __shfl_xor(re, m, 64);
+        im += __shfl_xor(im, m, 64);
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        wre[wave] = re;
+        wim[wave] = im;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partial[2 * u] = sre[0];
-        partial[2 * u + 1] = sim[0];
+        partial[2 * u] = (wre[0] + wre[1]) + (wre[2] + wre[3]);
+        partial[2 * u + 1] = (wim[0] + wim[1]) + (wim[2] + wim[3]);
     }
 }
 
@@ -1422,6 +1490,32 @@ void small_contract(const void *A, const void *Bt, void *C, int64_t units, int64
     const int64_t csize = c64 ? 8 : 16;
     const hipStream_t st = (hipStream_t)stream;
     if (units <= 0 || M <= 0 || N <= 0) return;
+    if (K == 8 && N == 8 && M >= 256) {
+        const int64_t blocks = (M + 255) / 256;
+        if (blocks >= ((int64_t)1 << 31)) fail(TNS_E_UNSUPPORTED, "small step with too many rows");
+        const ScatterStore none{};
+        for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+            const int64_t nu = std::min<int64_t>(65535, units - u0);
+            const dim3 grid((unsigned)blocks, (unsigned)nu);
+            if (c64) {
+                const float *a = (const float *)A + 2 * u0 * sA, *b = (const float *)Bt + 2 * u0 * sB;
+                float *c = (float *)C + 2 * u0 * sC;
+                if (sc) hipLaunchKernelGGL((k_small_fixed<float, 8, 8, true>), grid, dim3(256), 0, st, a, b, c, M,
+                                           sA, sB, sC, *sc);
+                else hipLaunchKernelGGL((k_small_fixed<float, 8, 8, false>), grid, dim3(256), 0, st, a, b, c, M,
+                                        sA, sB, sC, none);
+            } else {
+                const double *a = (const double *)A + 2 * u0 * sA, *b = (const double *)Bt + 2 * u0 * sB;
+                double *c = (double *)C + 2 * u0 * sC;
+                if (sc) hipLaunchKernelGGL((k_small_fixed<double, 8, 8, true>), grid, dim3(256), 0, st, a, b, c, M,
+                                           sA, sB, sC, *sc);
+                else hipLaunchKernelGGL((k_small_fixed<double, 8, 8, false>), grid, dim3(256), 0, st, a, b, c, M,
+                                        sA, sB, sC, none);
+            }
+            check_launch("small_fixed");
+        }
+        return;
+    }
     if (small_rows_fits(M, K, N, csize)) {
         const int RB = (int)small_rows_block(K, csize);
         const int64_t blocks = (M + RB - 1) / RB;
