@@ -149,6 +149,7 @@ def serving_run(T, ctx, torch, n_req=200, pool_size=24, cap_gpu_s=5.0, nominal_t
         t = time.perf_counter(); ctx.amplitudes(p, b); t4 = time.perf_counter() - t
         a = max((t4 - t1) / 3, 0.0)
         plans.append((name, circ, p, fl, (max(t1 - a, 0.0), a)))
+        print(f"[bench] serving pool: {name} planned, {p.info().n_slices} slices", file=sys.stderr, flush=True)
     pctx.close()
     reqs, rejected_work = [], 0
     for i in range(n_req):
@@ -177,6 +178,7 @@ def serving_run(T, ctx, torch, n_req=200, pool_size=24, cap_gpu_s=5.0, nominal_t
             if e.name != "TNS_E_ADMISSION":
                 raise
             rejected_mem += 1
+    print(f"[bench] serving: {len(handles)} requests submitted", file=sys.stderr, flush=True)
     total_amps, lat, lat_sliced = 0, [], []
     for k, h in handles:
         h.wait()
@@ -582,10 +584,12 @@ def slice_range_only(T, ctx, args, torch):
 
 
 def bench_batch(T, ctx, args, torch, workload, precision="c64", steps=3, warmup=1, n_bits=None,
-                compare=True, cpu=True):
+                compare=True, cpu=True, compare_bits=128, chunk=0):
     """A bitstring batch per step (workloads that need no cuts, e.g. the
     25-qubit grid): amplitudes/s, GEMM rates, the precision report against
-    complex128 and split-BF16, and the oracle's state vector beside it."""
+    complex128 and split-BF16 on the first compare_bits bitstrings, and the
+    oracle's state vector beside it.  chunk > 0 runs each step's batch in
+    calls of that many bitstrings, each reported as it ends (long batches)."""
     from circuits import config
     circ, bits = config(workload, n_bits=n_bits)
     plan = ctx.plan(circ, precision=precision)
@@ -595,10 +599,18 @@ def bench_batch(T, ctx, args, torch, workload, precision="c64", steps=3, warmup=
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     agg, amps = {}, None
+    pieces = [(a, min(len(bits), a + chunk)) for a in range(0, len(bits), chunk)] if chunk else [(0, len(bits))]
     for s in range(steps):
-        amps, st = ctx.amplitudes(plan, bits, stats=True)
-        for k, v in st.items():
-            agg[k] = agg.get(k, 0) + v
+        got = []
+        for a, b in pieces:
+            part, st = ctx.amplitudes(plan, bits[a:b], stats=True)
+            got.append(part)
+            for k, v in st.items():
+                agg[k] = agg.get(k, 0) + v
+            if chunk:
+                print(f"[bench] {workload} step {s}: bitstrings [{a}, {b}) done, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+        amps = np.concatenate(got)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_amp = steps * len(bits)
@@ -612,7 +624,7 @@ def bench_batch(T, ctx, args, torch, workload, precision="c64", steps=3, warmup=
                                      ("ms_bra", "ms_merge", "ms_contract", "ms_gemm", "ms_gemm3m",
                                       "ms_permute", "ms_small")}}
     if compare and precision == "c64":
-        sub = bits[:min(len(bits), 128)]
+        sub = bits[:min(len(bits), compare_bits)]
         p2 = ctx.plan(circ, precision="c128")
         ctx.amplitudes(p2, sub[:4])
         t = time.perf_counter()
@@ -660,10 +672,14 @@ def main():
                     help="timed steps; the headline splits its slices over them")
     ap.add_argument("--warmup", type=int, default=1, help="warm-up steps (one slice each on the headline)")
     ap.add_argument("--workload", default="diag53_d12",
-                    help="diag53_d12 (headline: one whole sliced amplitude) or a batch workload "
-                         "(grid3x4_d8, grid5x5_d10, grid8x13_d8)")
+                    help="diag53_d12 (headline: one whole sliced amplitude), a batch workload "
+                         "(grid3x4_d8, grid5x5_d10, grid8x13_d8), or legs (only the --legs)")
     ap.add_argument("--precision", default="c64", choices=["c64", "c128", "c64_bf16x3", "c64_bf16x6"])
     ap.add_argument("--bits", type=int, default=0, help="bitstrings per step of a batch workload")
+    ap.add_argument("--compare-bits", type=int, default=128,
+                    help="bitstrings of a batch workload compared against complex128 and split-BF16")
+    ap.add_argument("--chunk-bits", type=int, default=0,
+                    help="run a batch workload's steps in calls of this many bitstrings, reporting each")
     ap.add_argument("--slice-range", default="", help="A:B -- print the partial sum over slices [A, B) only")
     ap.add_argument("--legs", default="", help="comma list of extra legs: " + ",".join(LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -712,9 +728,12 @@ def main():
 
     if args.workload == "diag53_d12":
         line = headline_sliced(T, ctx, args, torch)
+    elif args.workload == "legs":
+        line = {"metric": "extra legs only (no headline)", "n_gpus": 1, "data": "synthetic"}
     else:
         r = bench_batch(T, ctx, args, torch, args.workload, args.precision, args.steps, args.warmup,
-                        args.bits or None, compare=not args.no_compare, cpu=not args.no_cpu_baseline)
+                        args.bits or None, compare=not args.no_compare, cpu=not args.no_cpu_baseline,
+                        compare_bits=args.compare_bits, chunk=args.chunk_bits)
         cpu = r.pop("cpu_oracle", None)
         line = {"metric": "amplitudes/s + achieved TFLOP/s, c64-MFMA vs c128, 53q depth-12; p50/p99 latency",
                 "value": r.pop("amps_per_s"), "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,

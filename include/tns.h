@@ -364,10 +364,13 @@ tns_status tns_request_latency(const tns_request *req, double *ms_total, double 
  * dims[e] (supplement, path section).  mode: tns_path_mode.  assumptions: as
  * in tns_plan_opts.  path_out[n] receives the order, score_out the summed
  * step cost (product of the dimensions of every bond carried by either
- * operand).  Fails with TNS_E_BAD_PATH when no admissible path exists. */
+ * operand).  max_intermediate > 0 (Algorithm 1 only): a size-aware bound
+ * beside the rank bound -- no intermediate may exceed that many elements
+ * (0 = no bound).  Fails with TNS_E_BAD_PATH when no admissible path
+ * exists. */
 tns_status tns_path_search(int32_t n, int32_t n_edges, const int32_t *edges,
                            const double *dims, int32_t mode, int32_t max_rank,
-                           int32_t assumptions, int64_t max_states,
+                           int32_t assumptions, int64_t max_states, double max_intermediate,
                            int32_t *path_out, double *score_out);
 
 /* Thread-local description of the last failure on this thread. */

@@ -178,3 +178,18 @@ def tree_optimum(n, edges, dims):
                 sub = (sub - 1) & mask
             best[mask] = val
     return best[(1 << n) - 1]
+
+
+def brute_force_bounded(n, edges, dims, max_size):
+    """Minimum score over the linear orders whose every intermediate (the
+    first tensor included) has at most ``max_size`` elements, and one order
+    reaching it; (None, None) when no order fits.  The size-aware bound that
+    can accompany the supplement's rank bound on intermediates."""
+    if n > 9:
+        raise ValueError("brute force is limited to N <= 9")
+    best, arg = None, None
+    for order in itertools.permutations(range(n)):
+        s, big = score(order, n, edges, dims)
+        if big <= max_size and (best is None or s < best):
+            best, arg = s, order
+    return best, (list(arg) if arg is not None else None)

@@ -139,7 +139,7 @@ def load_library(path: str = LIB_PATH):
         "tns_request_free": ([vp], i32),
         "tns_request_latency": ([vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)], i32),
-        "tns_path_search": ([i32, i32, vp, vp, i32, i32, i32, i64, vp,
+        "tns_path_search": ([i32, i32, vp, vp, i32, i32, i32, i64, ctypes.c_double, vp,
                              ctypes.POINTER(ctypes.c_double)], i32),
         "tns_last_error": ([], ctypes.c_char_p),
         "tns_version": ([], ctypes.c_char_p),
@@ -439,13 +439,15 @@ class Context:
 
 
 def path_search(n: int, edges, dims, mode: str = "algorithm1", max_rank: int = 0,
-                assumptions: bool = True, max_states: int = 0):
-    """(order, score) of a linear contraction path over a weighted graph."""
+                assumptions: bool = True, max_states: int = 0, max_intermediate: float = 0.0):
+    """(order, score) of a linear contraction path over a weighted graph;
+    max_intermediate > 0 bounds every intermediate's size (Algorithm 1)."""
     e = np.ascontiguousarray(edges, np.int32).reshape(-1, 2)
     d = np.ascontiguousarray(dims, np.float64)
     out = np.zeros(n, np.int32)
     score = ctypes.c_double()
     _check(load_library().tns_path_search(n, e.shape[0], e.ctypes.data, d.ctypes.data,
                                           PATH_MODE[mode], max_rank, 1 if assumptions else 0,
-                                          max_states, out.ctypes.data, ctypes.byref(score)))
+                                          max_states, float(max_intermediate), out.ctypes.data,
+                                          ctypes.byref(score)))
     return out.tolist(), score.value

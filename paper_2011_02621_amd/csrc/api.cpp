@@ -771,7 +771,7 @@ tns_status tns_request_latency(const tns_request *r, double *ms_total, double *m
 
 tns_status tns_path_search(int32_t n, int32_t n_edges, const int32_t *edges, const double *dims,
                            int32_t mode, int32_t max_rank, int32_t assumptions, int64_t max_states,
-                           int32_t *path_out, double *score_out) {
+                           double max_intermediate, int32_t *path_out, double *score_out) {
     return guard([&] {
         if (n < 1 || n > TNS_MAX_QUBITS) fail(TNS_E_INVALID_ARG, "n out of range");
         if (n_edges < 0 || (n_edges > 0 && (!edges || !dims)) || !path_out)
@@ -786,7 +786,10 @@ tns_status tns_path_search(int32_t n, int32_t n_edges, const int32_t *edges, con
             D.push_back(dims[e]);
         }
         if (mode != TNS_PATH_GREEDY && mode != TNS_PATH_ALGORITHM1) fail(TNS_E_INVALID_ARG, "unknown mode");
-        PathResult r = path_search(n, E, D, mode, max_rank, assumptions != 0, max_states);
+        if (!(max_intermediate >= 0)) fail(TNS_E_INVALID_ARG, "max_intermediate must be >= 0");
+        PathResult r = path_search(n, E, D, mode, max_rank, assumptions != 0, max_states, max_intermediate);
+        if (max_intermediate > 0 && mode == TNS_PATH_ALGORITHM1 && r.peak > max_intermediate * (1 + 1e-12))
+            fail(TNS_E_BAD_PATH, "no path found with every intermediate within max_intermediate");
         for (int i = 0; i < n; ++i) path_out[i] = r.order[i];
         if (score_out) *score_out = r.score;
     });

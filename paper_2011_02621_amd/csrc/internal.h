@@ -193,9 +193,11 @@ struct PathResult {
     bool complete = true;
 };
 
+// max_size > 0: Algorithm 1 admits no intermediate above max_size elements
+// (the size-aware bound beside the rank bound M)
 PathResult path_search(int n, const std::vector<std::pair<int, int>> &edges,
                        const std::vector<double> &dims, int mode, int max_rank,
-                       bool assumptions, int64_t max_states);
+                       bool assumptions, int64_t max_states, double max_size = 0);
 double path_score(int n, const std::vector<std::pair<int, int>> &edges,
                   const std::vector<double> &dims, const std::vector<int> &order,
                   double *peak, int *max_rank);

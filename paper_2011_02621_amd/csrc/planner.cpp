@@ -301,7 +301,7 @@ struct QCmp {
 // start (boundary qubits), the rank of intermediates (<= M) and connectivity
 // (connected, or connected plus one isolated qubit that the next step joins).
 PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_states,
-                      double upper, const PathResult *fallback) {
+                      double upper, const PathResult *fallback, double max_size) {
     const int n = g.n;
     std::vector<Node> arena;
     arena.reserve(1 << 16);
@@ -314,6 +314,11 @@ PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_s
     for (int v = 0; v < n; ++v) {
         bool boundary = !assumptions || (int)g.nbr[v].size() < maxdeg;
         if (!boundary) continue;
+        if (max_size > 0) {
+            double sz = 1;
+            for (int e : g.legs[v]) sz *= g.d[e];
+            if (sz > max_size * (1 + 1e-12)) continue;
+        }
         Node nd;
         nd.set.set(v);
         nd.score = 0;
@@ -365,6 +370,8 @@ PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_s
             }
             int nrank = rank - shared + fresh;
             if (assumptions && nrank > max_rank) return;
+            // size-aware bound: no intermediate above max_size elements
+            if (max_size > 0 && size / K * N > max_size * (1 + 1e-12)) return;
             double ns = cur.score + size * N;
             if (ns > upper) return;
             Node nd;
@@ -419,16 +426,18 @@ PathResult algorithm1(const PG &g, int max_rank, bool assumptions, int64_t max_s
 
 PathResult path_search(int n, const std::vector<std::pair<int, int>> &edges,
                        const std::vector<double> &dims, int mode, int max_rank,
-                       bool assumptions, int64_t max_states) {
+                       bool assumptions, int64_t max_states, double max_size) {
     PG g = make_pg(n, edges, dims);
     PathResult gr = greedy(g);
     if (mode == TNS_PATH_GREEDY) return gr;
     if (mode != TNS_PATH_ALGORITHM1) fail(TNS_E_INVALID_ARG, "unknown path mode");
     int M = max_rank > 0 ? max_rank : gr.max_rank;
-    double upper = assumptions ? gr.score : std::numeric_limits<double>::infinity();
+    // the greedy path bounds the search only when it is itself admissible
+    const bool greedy_fits = !(max_size > 0) || gr.peak <= max_size * (1 + 1e-12);
+    double upper = assumptions && greedy_fits ? gr.score : std::numeric_limits<double>::infinity();
     // an exhausted state budget returns the greedy path, marked incomplete
     // (with the assumptions off the search is exact and has no other bound)
-    PathResult r = algorithm1(g, M, assumptions, max_states > 0 ? max_states : 4000000, upper, &gr);
+    PathResult r = algorithm1(g, M, assumptions, max_states > 0 ? max_states : 4000000, upper, &gr, max_size);
     r.max_rank = std::max(r.max_rank, 0);
     // report the rank bound actually used by the search
     if (assumptions) r.max_rank = M;
@@ -1266,9 +1275,12 @@ static void choose_cuts_and_path(Plan &p) {
     }
     p.search_complete = true;
     p.search_states = 0;
-    auto search = [&](const std::vector<double> &d, int mode) {
+    // searches on a sliced network also keep every intermediate within the
+    // limit (the size-aware bound); the unsliced search, which places the
+    // cuts, does not
+    auto search = [&](const std::vector<double> &d, int mode, double max_size = 0) {
         PathResult r = path_search(c.n, E, d, mode, p.opts.max_rank, p.opts.path_assumptions != 0,
-                                   p.opts.max_search_states);
+                                   p.opts.max_search_states, max_size);
         if (mode == TNS_PATH_ALGORITHM1) {
             p.search_complete = p.search_complete && r.complete;
             p.search_states += r.states;
@@ -1285,14 +1297,24 @@ static void choose_cuts_and_path(Plan &p) {
         p.path = r;
     } else if (p.opts.n_cuts >= 0) {
         p.cuts = given;
-        p.path = search(dims_with_cuts(p, p.cuts), p.opts.path_mode);
+        p.path = search(dims_with_cuts(p, p.cuts), p.opts.path_mode, limit);
     } else {
         std::vector<double> d0 = dims_with_cuts(p, {});
         PathResult best_path;
         Sliced best;
         best.total = std::numeric_limits<double>::infinity();
+        // candidates are ranked by the cost they reach once side branches
+        // are added (the linear cost when branches are off)
         auto consider = [&](const PathResult &r, const Sliced &s) {
-            if (s.peak <= limit && s.total < best.total) { best = s; best_path = r; }
+            if (!(s.peak <= limit)) return;
+            Sliced t = s;
+            if (p.opts.path_branches) {
+                double sc = 0;
+                choose_branches(c, dims_with_cuts(p, s.cuts), r.order, std::log2(limit),
+                                std::min(std::log2(limit), std::log2((double)kBranchPeakElems)), &sc);
+                t.total = sc * s.slices;
+            }
+            if (t.total < best.total) { best = t; best_path = r; }
         };
         std::vector<int> modes{TNS_PATH_GREEDY};
         if (p.opts.path_mode != TNS_PATH_GREEDY) modes.push_back(p.opts.path_mode);
@@ -1303,7 +1325,7 @@ static void choose_cuts_and_path(Plan &p) {
             if (s.cuts.empty()) continue;
             // re-plan on the sliced network (the paper's order of operations)
             std::vector<double> ds = dims_with_cuts(p, s.cuts);
-            PathResult r2 = search(ds, mode);
+            PathResult r2 = search(ds, mode, limit);
             Sliced s2 = cuts_for_order(p, r2.order, s.cuts, limit);
             consider(r2, s2);
         }
@@ -1316,7 +1338,7 @@ static void choose_cuts_and_path(Plan &p) {
                 r.order = order;
                 consider(r, sa);
                 if (p.opts.path_mode != TNS_PATH_GREEDY) {
-                    PathResult r3 = search(dims_with_cuts(p, sa.cuts), p.opts.path_mode);
+                    PathResult r3 = search(dims_with_cuts(p, sa.cuts), p.opts.path_mode, limit);
                     consider(r3, cuts_for_order(p, r3.order, sa.cuts, limit));
                 }
             }

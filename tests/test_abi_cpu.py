@@ -272,6 +272,28 @@ def test_algorithm1_without_assumptions_is_optimal(seed):
     assert score == best
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_size_bounded_algorithm1_is_optimal_among_bounded_orders(seed):
+    # with the assumptions off Algorithm 1 is exact; with a size bound it is
+    # exact over the orders whose every intermediate fits (oracle brute force)
+    n = 7
+    edges, dims = _random_graph(200 + seed, n)
+    _, free_peak = paths.score(paths.brute_force(n, edges, dims)[1], n, edges, dims)
+    sizes = sorted({paths.score(list(o), n, edges, dims)[1]
+                    for o in [np.random.default_rng(seed + k).permutation(n).tolist() for k in range(40)]})
+    for bound in sizes[: len(sizes) // 2 + 1]:
+        best, _ = paths.brute_force_bounded(n, edges, dims, bound)
+        if best is None:
+            with pytest.raises(T.TnsError):
+                T.path_search(n, edges, dims, mode="algorithm1", assumptions=False, max_intermediate=bound)
+            continue
+        order, score = T.path_search(n, edges, dims, mode="algorithm1", assumptions=False,
+                                     max_intermediate=bound)
+        s, peak = paths.score(order, n, edges, dims)
+        assert s == score == best and peak <= bound
+    assert free_peak > 0
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_restricted_searches_are_admissible(seed):
     n = 8

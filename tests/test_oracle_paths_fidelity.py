@@ -84,6 +84,18 @@ def test_tree_score_without_windows_is_linear(seed):
     assert paths.tree_optimum(g.n, g.edges, dims) <= paths.subset_dp(g.n, g.edges, dims)
 
 
+def test_bounded_brute_force_by_hand():
+    # the 3-site chain 0 -(a=2)- 1 -(b=3)- 2: orders, (score, largest tensor):
+    # 2,1,0 -> (8, 3): tensors {b}=3, {a}=2, scalar;  1,2,0 -> (8, 6);
+    # 0,1,2 -> (9, 3); 1,0,2 -> (9, 6); 0,2,1 -> (12, 6); 2,0,1 -> (12, 6).
+    # A bound of 3 elements keeps 2,1,0 and 0,1,2; a bound of 2 keeps none
+    # (only site 0 starts within it, and its next tensor has 3 or 6 elements).
+    edges, dims = [(0, 1), (1, 2)], [2, 3]
+    assert paths.brute_force_bounded(3, edges, dims, 6)[0] == 8
+    assert paths.brute_force_bounded(3, edges, dims, 3) == (8, [2, 1, 0])
+    assert paths.brute_force_bounded(3, edges, dims, 2) == (None, None)
+
+
 def test_intermediate_size_tracks_open_legs():
     g = grid(2, 3)
     dims = [2] * len(g.edges)
