@@ -141,14 +141,20 @@ def serving_run(T, ctx, torch, n_req=200, pool_size=24, cap_gpu_s=5.0, nominal_t
             p.close()
             plans.append((name, circ, None, fl, None))
             continue
-        # service-time model o + a * n from one and four bitstrings
-        b = bitstrings(circ.n, 4, 9000)
+        # service-time model: a call costs o + a * n (one and sixteen
+        # bitstrings, synchronous); a served request is cut into work items
+        # as the library does (about 4e13 flops, at most 1024 bitstrings,
+        # slice ranges for single heavy bitstrings) and pays o per item
+        b = bitstrings(circ.n, 16, 9000)
         ctx.amplitudes(p, b[:1])
         torch.cuda.synchronize()
         t = time.perf_counter(); ctx.amplitudes(p, b[:1]); t1 = time.perf_counter() - t
-        t = time.perf_counter(); ctx.amplitudes(p, b); t4 = time.perf_counter() - t
-        a = max((t4 - t1) / 3, 0.0)
-        plans.append((name, circ, p, fl, (max(t1 - a, 0.0), a)))
+        t = time.perf_counter(); ctx.amplitudes(p, b); t16 = time.perf_counter() - t
+        a = max((t16 - t1) / 15, 0.0)
+        n_sl = int(p.info().n_slices)
+        nb_item = int(min(1024, max(1, 4e13 // max(fl, 1.0))))
+        ns_item = n_sl if nb_item > 1 else int(min(n_sl, max(1, 4e13 // max(fl / n_sl, 1.0))))
+        plans.append((name, circ, p, fl, (max(t1 - a, 0.0), a, nb_item, -(-n_sl // ns_item))))
         print(f"[bench] serving pool: {name} planned, {p.info().n_slices} slices", file=sys.stderr, flush=True)
     pctx.close()
     reqs, rejected_work = [], 0
@@ -159,7 +165,9 @@ def serving_run(T, ctx, torch, n_req=200, pool_size=24, cap_gpu_s=5.0, nominal_t
         if p is None or fl * nb / (nominal_tflops * 1e12) > cap_gpu_s:
             rejected_work += 1
             continue
-        reqs.append((k, bitstrings(circ.n, nb, 20000 + i), model[0] + model[1] * nb))
+        o, a, nb_item, chunks = model
+        items = -(-nb // nb_item) * chunks
+        reqs.append((k, bitstrings(circ.n, nb, 20000 + i), o * items + a * nb))
     mean_service = float(np.mean([r[2] for r in reqs]))
     rate = load / mean_service
     gaps = rng.exponential(1.0 / rate, size=len(reqs))
@@ -468,13 +476,22 @@ def cpu_baseline_sliced(circ_full, lattice_sub, depth, seed, budget_s=4.0):
 
 def headline_sliced(T, ctx, args, torch):
     """One whole amplitude of a sliced workload, its slices spread over the
-    timed steps (see the module docstring)."""
+    timed steps (see the module docstring).  With --open K, the K qubits the
+    path absorbs last keep their output bit open: one contraction then yields
+    the 2^K amplitudes of all bitstrings that agree elsewhere (a correlated
+    batch, 4096 bitstrings at K = 12), computed whole the same way."""
     from circuits import config, diagonal53
     circ, bits = config(args.workload, n_bits=1)
     t = time.perf_counter()
-    plan = ctx.plan(circ, precision=args.precision)
+    oq = None
+    if args.open:
+        base = T.Context(-1).plan(circ, precision=args.precision)
+        oq = [int(q) for q in base.info().path[-args.open:]]
+        base.close()
+    plan = ctx.plan(circ, precision=args.precision, open_qubits=oq)
     t_plan = time.perf_counter() - t
     info = plan.info()
+    per = 1 << len(oq or [])
     S, K = int(info.n_slices), args.steps
     if K > S:
         raise SystemExit(f"--steps {K} exceeds the plan's {S} slices: each step takes a range of slices")
@@ -488,15 +505,15 @@ def headline_sliced(T, ctx, args, torch):
     warm_parts = {}
     for w in range(args.warmup):
         sl = w % S
-        warm_parts[sl] = ctx.amplitudes(plan, bits, slices=(sl, sl + 1))[0]
+        warm_parts[sl] = ctx.amplitudes(plan, bits, slices=(sl, sl + 1)).reshape(-1)
         print(f"[bench] warmup {w} (slice {sl}) done", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    agg, amp, per_step = {}, 0.0 + 0.0j, []
+    agg, amp, per_step = {}, np.zeros(per, np.complex128), []
     for i, (a, b) in enumerate(ranges):
         part, st = ctx.amplitudes(plan, bits, stats=True, slices=(a, b))
-        amp += complex(part[0])
+        amp += part.reshape(-1)
         for k, v in st.items():
             agg[k] = agg.get(k, 0) + v
         per_step.append(st["ms_total"])
@@ -508,20 +525,22 @@ def headline_sliced(T, ctx, args, torch):
 
     line = {
         "metric": "amplitudes/s + achieved TFLOP/s, c64-MFMA vs c128, 53q depth-12; p50/p99 latency",
-        "value": round(1.0 / dt, 8), "unit": "amplitudes/s", "n_gpus": 1, "steps": K,
+        "value": round(per / dt, 8), "unit": "amplitudes/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(dt / K * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"c64": "c64 (fp32 mfma)", "c128": "c128 (fp64 mfma)",
                   "c64_bf16x3": "c64 (split-bf16 x3)", "c64_bf16x6": "c64 (split-bf16 x6)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "qubits": circ.n, "cycles": circ.depth,
-                   "circuit_seed": 3, "bitstring_seed": 103, "bitstrings": 1,
+                   "circuit_seed": 3, "bitstring_seed": 103, "bitstrings": per,
+                   "open_qubits": oq or [],
                    "precision": args.precision, "split_cycle": int(info.split_cycle),
                    "cut_edges": info.cut_edges.tolist(), "n_slices": S, "slices_timed": covered,
                    "slices_per_step": [ranges[0][1] - ranges[0][0], max(b - a for a, b in ranges)],
                    "peak_elems": int(info.peak_elems), "flops_per_amp": info.flops_per_amp},
-        "s_per_amplitude": round(dt, 3),
-        "amplitude": [amp.real, amp.imag],
+        "s_per_contraction": round(dt, 3),
+        "amplitude": [amp[0].real, amp[0].imag] if per == 1 else None,
+        "amplitudes_sum_abs2": float(np.sum(np.abs(amp) ** 2)) if per > 1 else None,
         "achieved_tflops_whole_path": round(info.flops_per_amp / dt / 1e12, 3),
         "roofline": gemm_roofline(agg, args.precision, args.workload),
         "cpu_baseline": None,
@@ -535,15 +554,15 @@ def headline_sliced(T, ctx, args, torch):
         # complex128 on the same split, path and cuts: one slice timed, and
         # its partial sum against the complex64 one of the warm-up
         same = dict(split_cycle=int(info.split_cycle), path=info.path.tolist(),
-                    cuts=info.cut_edges.tolist())
+                    cuts=info.cut_edges.tolist(), open_qubits=oq)
         p2 = ctx.plan(circ, precision="c128", **same)
         t = time.perf_counter()
-        ref = ctx.amplitudes(p2, bits, slices=(0, 1))[0]
+        ref = ctx.amplitudes(p2, bits, slices=(0, 1)).reshape(-1)
         t2 = time.perf_counter() - t
         got = warm_parts[0]
-        line["c128"] = {"s_per_slice": round(t2, 3), "est_s_per_amplitude": round(t2 * S, 1),
-                        "slice0_partial": [ref.real, ref.imag],
-                        "slice0_rel_diff_c64_vs_c128": float(abs(got - ref) / abs(ref))}
+        line["c128"] = {"s_per_slice": round(t2, 3), "est_s_per_contraction": round(t2 * S, 1),
+                        "slice0_partial": [ref[0].real, ref[0].imag],
+                        "slice0_rel_l2_c64_vs_c128": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
         p2.close()
         print(f"[bench] c128 slice 0: {t2:.2f} s", file=sys.stderr, flush=True)
 
@@ -681,6 +700,8 @@ def main():
     ap.add_argument("--chunk-bits", type=int, default=0,
                     help="run a batch workload's steps in calls of this many bitstrings, reporting each")
     ap.add_argument("--slice-range", default="", help="A:B -- print the partial sum over slices [A, B) only")
+    ap.add_argument("--open", type=int, default=0,
+                    help="headline as a correlated batch: the last K qubits of the path left open (2^K amplitudes)")
     ap.add_argument("--legs", default="", help="comma list of extra legs: " + ",".join(LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
