@@ -330,9 +330,10 @@ tns_status tns_sample_frugal(tns_ctx *ctx, const tns_plan *plan, int64_t n_batch
  * independent (bitstring, slice) units of the overlap paragraph's cutting),
  * shaped at submission to about 4e13 contraction flops each and to fit
  * memory.  The context's worker threads, one HIP stream and workspace each,
- * take items round-robin over the active requests, so requests that arrive
- * while others run are admitted as workers and memory free up and their
- * items overlap on the device.  Memory: the first tns_submit starts the
+ * take the next item of the active request with the least planned work left
+ * (shortest remaining work first), so requests that arrive while others run
+ * are admitted as workers and memory free up, short requests are not held
+ * behind long ones, and items of several requests overlap on the device.  Memory: the first tns_submit starts the
  * workers; a quarter of the context's HBM budget stays with synchronous
  * calls on the same context (a larger cached synchronous workspace is
  * released) and the rest is a pool the workers share; an item starts only

@@ -50,10 +50,12 @@ static void hip_check(hipError_t e, const char *what) {
 // ----------------------------------------------------------------------------
 // serving.  A request is cut into work items, each a range of bitstrings
 // times a range of slices, i.e. a block of (bitstring, slice) units.  Worker
-// threads (one HIP stream and workspace each) take items round-robin over
+// threads (one HIP stream and workspace each) take items from
 // the active requests, so a request that arrives while others run starts as
 // soon as a worker and the memory for one of its items are free, and its
-// items overlap with theirs on the device.
+// items overlap with theirs on the device.  A free worker takes the next item
+// of the request with the least planned work left (shortest remaining work
+// first).
 //
 // Memory: the workers share a pool, the context's budget less the share kept
 // for synchronous calls.  A worker holds a reservation for the workspace it
@@ -76,6 +78,7 @@ struct Request {
     int64_t n_schunks = 1;               // slice ranges per bitstring range
     int64_t n_items = 0, next_item = 0, finished_items = 0;
     uint64_t item_bytes = 0;             // workspace of one item
+    double item_flops = 0;               // planned contraction flops of one item
     std::vector<double> part;            // [n][n_schunks][opu][2] when n_schunks > 1
     int running = 0;                     // items in flight
     volatile int cancel = 0;
@@ -170,12 +173,13 @@ struct Server {
     bool pick(int w, Item &it, bool &newly_blocked) {
         newly_blocked = false;
         if (active.empty()) return false;
-        auto cur = rr == active.end() ? active.begin() : rr;
+        // shortest remaining work first: the request with the fewest planned
+        // flops left whose next item fits the memory pool (ties: the earlier
+        // request), so short requests are not held behind long ones
         bool blocked = false;
-        for (size_t tries = 0; tries < active.size(); ++tries) {
-            Request *r = *cur;
-            ++cur;
-            if (cur == active.end()) cur = active.begin();
+        Request *best = nullptr;
+        double best_left = 0;
+        for (Request *r : active) {
             if (r->next_item >= r->n_items || r->status != TNS_OK || r->cancel) continue;
             const bool reuse = held_plan[w] == r->plan && held[w] >= r->item_bytes;
             const uint64_t mine = reuse ? held[w] : r->item_bytes;
@@ -183,6 +187,16 @@ struct Server {
                 blocked = true;
                 continue;
             }
+            const double left = (double)(r->n_items - r->next_item) * r->item_flops;
+            if (!best || left < best_left) {
+                best = r;
+                best_left = left;
+            }
+        }
+        if (best) {
+            Request *r = best;
+            const bool reuse = held_plan[w] == r->plan && held[w] >= r->item_bytes;
+            const uint64_t mine = reuse ? held[w] : r->item_bytes;
             it = Item{};
             it.r = r;
             it.release_first = !reuse && held[w] > 0;
@@ -201,7 +215,6 @@ struct Server {
                 r->started = true;
                 r->t_start = clk::now();
             }
-            rr = cur;
             return true;
         }
         if (blocked && !pressure) {
@@ -338,8 +351,10 @@ struct Server {
 };
 
 // Item shape of a request: about kItemFlops of contraction per item (a few
-// tenths of a second on the device), at most 64 bitstrings, and a workspace
-// that fits the pool.
+// tenths of a second on the device), at most 1024 bitstrings (light circuits
+// take whole requests, so the fixed cost of a call -- the bra evolution's
+// launches, the host round trip -- is paid once), and a workspace that fits
+// the pool.
 constexpr double kItemFlops = 4e13;
 
 static void shape_items(Request *r, const Server &sv, double item_flops) {
@@ -347,7 +362,7 @@ static void shape_items(Request *r, const Server &sv, double item_flops) {
     const Plan &p = *r->plan;
     const double per_slice = p.flops_per_amp / (double)p.n_slices;
     int64_t nb = (int64_t)std::floor(kItemFlops / std::max(p.flops_per_amp, 1.0));
-    nb = std::max<int64_t>(1, std::min<int64_t>({nb, 64, r->n}));
+    nb = std::max<int64_t>(1, std::min<int64_t>({nb, 1024, r->n}));
     int64_t ns = p.n_slices;
     if (nb == 1) ns = std::max<int64_t>(1, std::min<int64_t>(p.n_slices, (int64_t)(kItemFlops / std::max(per_slice, 1.0))));
     while (call_workspace_bytes(p, nb, ns, sv.pool) > sv.pool && (nb > 1 || ns > 1)) {
@@ -359,6 +374,7 @@ static void shape_items(Request *r, const Server &sv, double item_flops) {
     r->n_schunks = (p.n_slices + ns - 1) / ns;
     r->n_items = ((r->n + nb - 1) / nb) * r->n_schunks;
     r->item_bytes = call_workspace_bytes(p, nb, ns, sv.pool);
+    r->item_flops = p.flops_per_amp / (double)p.n_slices * (double)nb * (double)ns;
 }
 
 }  // namespace tns
