@@ -146,8 +146,8 @@ typedef struct {
     const int64_t *step_n;          /* [n_steps] new-leg product */
     const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM (real embedding), 1 small,
                                        2 final dot, 3 MFMA GEMM in the three-multiplication
-                                       form (complex64 steps with even K >= 128, N >= 64,
-                                       M >= 64) */
+                                       form (complex64 steps with even K >= 128 or even
+                                       K <= 32, N >= 64, M >= 64) */
     const int32_t *step_permute;    /* [n_steps] 0 no permute, 1 permute launch, 2 permute done
                                        by the previous step's store (fused; a GEMM, or a
                                        small-bond step with at least 64 rows) */
@@ -157,7 +157,8 @@ typedef struct {
     int32_t n_cuts;
     const int32_t *cut_edges;       /* [n_cuts] */
     int64_t n_slices;
-    double flops_per_amp;           /* 8 * sum over slices and steps of M*K*N */
+    double flops_per_amp;           /* 8 * sum over slices and steps of M*K*N, the shared
+                                       prefix steps counted once */
     double gemm_bytes_per_amp;      /* element bytes * sum (MK + KN + MN) */
     double permute_bytes_per_amp;   /* 2 * element bytes * elements of the permute launches */
     double path_score;              /* sum of M*K*N of one slice (the supplement's score) */
@@ -183,6 +184,12 @@ typedef struct {
     const int32_t *step_chain;      /* [n_steps] 0 main path, w + 1 a step of branch w */
     double linear_score;            /* sum of M*K*N of one slice along `path` as a single linear
                                        path (path_score is that of the plan with its branches) */
+    int32_t n_prefix_steps;         /* leading entries of step_* whose tensors carry no cut bond
+                                       (every slice has the same ones: overlap paragraph,
+                                       cutting): computed once per bitstring and copied to each
+                                       (bitstring, slice) unit; 0 without cuts or when only the
+                                       first tensor would be shared */
+    double prefix_flops_per_amp;    /* 8 * sum of M*K*N over those steps (in flops_per_amp once) */
 } tns_plan_info;
 
 typedef struct {

@@ -89,7 +89,8 @@ class _PlanInfo(ctypes.Structure):
                 ("n_branches", ctypes.c_int32),
                 ("branch_windows", ctypes.POINTER(ctypes.c_int32)),
                 ("step_chain", ctypes.POINTER(ctypes.c_int32)),
-                ("linear_score", ctypes.c_double)]
+                ("linear_score", ctypes.c_double), ("n_prefix_steps", ctypes.c_int32),
+                ("prefix_flops_per_amp", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -116,6 +117,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with python -m paper_2011_02621_amd.build")
+    # One HIP runtime per process: torch carries its own copy of the runtime
+    # library, and two copies loaded side by side each see the GPU only if
+    # the other has not opened it.  With torch imported first, the library's
+    # dependency resolves to the copy already loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     sig = {
@@ -206,6 +215,8 @@ class PlanInfo:
     branch_windows: np.ndarray   # [n_branches][2]
     step_chain: np.ndarray
     linear_score: float
+    n_prefix_steps: int          # leading steps shared by every slice (computed once per bitstring)
+    prefix_flops_per_amp: float
 
 
 def _arr(ptr, n, dtype):
@@ -238,7 +249,8 @@ class Plan:
             inf.n_fused_bra, bool(inf.search_complete), inf.search_states, inf.max_rank_used,
             inf.fidelity, inf.n_samples, inf.precision, _arr(inf.open_qubits, inf.n_open, np.int32),
             _arr(inf.branch_windows, 2 * inf.n_branches, np.int32).reshape(-1, 2),
-            _arr(inf.step_chain, ns, np.int32), inf.linear_score)
+            _arr(inf.step_chain, ns, np.int32), inf.linear_score, inf.n_prefix_steps,
+            inf.prefix_flops_per_amp)
 
     def close(self):
         if self._h:

@@ -544,6 +544,10 @@ tns_status tns_plan_info_get(const tns_plan *p, tns_plan_info *o) {
         o->branch_windows = p->info_branch_windows.data();
         o->step_chain = p->info_chain.data();
         o->linear_score = p->linear_score;
+        int32_t np = 0;
+        for (int m = 0; m < p->prefix_steps; ++m) np += p->steps[m].start ? 0 : 1;
+        o->n_prefix_steps = np;
+        o->prefix_flops_per_amp = p->prefix_flops;
     });
 }
 

@@ -134,11 +134,13 @@ inline int64_t small_rows_block(int64_t K, int64_t csize) {
 }
 // csize: bytes per complex element (8 for complex64, 16 for complex128)
 // complex64 MFMA steps that take the three-multiplication GEMM (kernel
-// class 3): even K of at least 128 and at least 64 complex columns (its block
-// is 128 x 64); measured with fused stores: +12 % from K = 256 up, +2-7 % at
-// K = 128, a loss of 3-10 % at K <= 64 (the epilogue then dominates)
+// class 3) and at least 64 complex columns: even K of at least 128 (its
+// block is 128 x 64; measured with fused stores: +12 % from K = 256 up,
+// +2-7 % at K = 128, a loss of 3-10 % at K = 64), or even K of at most 32,
+// where a kernel that keeps A in registers and walks the columns (the
+// output-bound short-K steps) takes them
 inline bool gemm_3m_fits(int64_t M, int64_t K, int64_t N) {
-    return K % 2 == 0 && K >= 128 && N >= 64 && M >= 64;
+    return K % 2 == 0 && (K >= 128 || K <= 32) && N >= 64 && M >= 64;
 }
 inline bool small_rows_fits(int64_t M, int64_t K, int64_t N, int64_t csize) {
     return M >= 64 && small_rows_block(K, csize) >= 8 && N * (K + 1) * csize <= kSmallRowsB;
@@ -262,6 +264,13 @@ struct Plan {
     int64_t unit_stride = 0;             // boundary buffer stride per unit (peak, 32-aligned)
     int64_t branch_stride = 0;           // branch buffer stride per unit (32-aligned)
     int64_t max_b_elems = 0;             // largest B operand (complex elements)
+    // Slice prefix: steps [0, prefix_steps) are on the main path and carry no
+    // cut bond, so every slice computes the same tensors there; they run once
+    // per bitstring and their result (prefix_elems per bitstring) is copied to
+    // each (bitstring, slice) unit.  0 when there is nothing to share.
+    int prefix_steps = 0;
+    int64_t prefix_elems = 0;
+    double prefix_flops = 0;             // 8 M K N summed over the prefix steps
     double flops_per_amp = 0, gemm_bytes_per_amp = 0, permute_bytes_per_amp = 0;
     double path_score = 0;
 
@@ -374,7 +383,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
                     int64_t slice_end = -1, const FrugalAccept *frugal = nullptr,
                     const uint8_t *bits_dev = nullptr, double *amps_dev = nullptr);
-int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget);
+int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget, int64_t n_sl);
 // Workspace bytes a fresh workspace holds after run_amplitudes(n bitstrings,
 // n_sl slices) under `budget`.
 uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t budget);
@@ -410,6 +419,10 @@ void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t
 void build_b(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
              int64_t slice0, int64_t site_stride, const SliceMap &sm, const Gather &g, int64_t K,
              int64_t N, int c64, int embed, void *stream);
+// out[u][i] = pre[(u0 + u) / nper][i], i < elems (unit stride out_us): each
+// (bitstring, slice) unit starts from its bitstring's slice-prefix tensor.
+void expand_prefix(const void *pre, void *out, int64_t units, int64_t u0, int64_t nper, int64_t elems,
+                   int64_t out_us, int elem_bytes, void *stream);
 // sc: when non-null, C is stored through the fused-store tables (the row
 // index includes every row of the unit, C is the unit's base).  mode 4 (the
 // three-multiplication form) takes Bt as the plain complex [N][K].

@@ -158,6 +158,18 @@ __global__ __launch_bounds__(256) void k_permute_tiled(const E *__restrict__ in,
 
 // unit u of this launch is global unit ug = u0 + u = bitstring * n_slices + j,
 // computing slice slice0 + j
+// the slice prefix of a unit's bitstring copied into the unit's buffer
+template <typename E>
+__global__ void k_expand_prefix(const E *__restrict__ pre, E *__restrict__ out, int64_t units, int64_t u0,
+                                int64_t nper, int64_t elems, int64_t out_us) {
+    const int64_t total = units * elems;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / elems, i = t - u * elems;
+        out[u * out_us + i] = pre[((u0 + u) / nper) * elems + i];
+    }
+}
+
 template <typename E>
 __global__ void k_gather_site(const E *__restrict__ site, E *__restrict__ out, int64_t units,
                               int64_t u0, int64_t n_slices, int64_t slice0, int64_t site_stride,
@@ -259,12 +271,6 @@ __device__ __forceinline__ void split_store(__bf16 *dst, int part_stride, v4f v)
     if (NSPLIT == 3) *reinterpret_cast<bf16x4 *>(dst + 2 * part_stride) = l;
 }
 
-// Fused store of one wave's tile (WR rows, BJ slices of CW complex columns),
-// staged through LDS: stage(j) writes slice j into stg (row stride SLD
-// reals), then each lane stores whole complex values V in the order in
-// which the target is contiguous.  64 is a multiple of WR and of CW, so a
-// lane keeps one row (row order) or one column (column order) across its
-// stores, and the table lookups of that index are made once.
 // Orders one wave's LDS stores before its own later LDS loads (and the loads
 // before its next stores): the staging area of the fused store is private to
 // the wave, so no block barrier is needed.
@@ -274,53 +280,73 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Target offsets of a block's fused store, read from the tables once and
+// kept in LDS: ofs_r[i] for row rb0 + i of the launch (-1 past M), ofs_c[c]
+// for complex column cb0 + c (-1 past N).  Called by all 256 threads before
+// the k-loop, whose barriers publish it.  The store loops then read offsets
+// from LDS only: a table read from global memory between two stores waits
+// on the vector-memory counter, which also counts the wave's stores still in
+// flight, and so would hold every store until the previous ones completed.
+__device__ __forceinline__ void fused_offsets(int64_t *ofs_r, int nr, int64_t *ofs_c, int nc,
+                                              const ScatterStore &sc, int64_t row0, int64_t rb0, int64_t M,
+                                              int64_t cb0, int64_t N, int tid) {
+    const int64_t mask = ((int64_t)1 << sc.shift) - 1;
+    for (int i = tid; i < nr; i += 256) {
+        const int64_t row = rb0 + i;
+        int64_t v = -1;
+        if (row < M) {
+            const int64_t gr = row0 + row;
+            v = sc.fa[gr >> sc.shift] + sc.fb[gr & mask];
+        }
+        ofs_r[i] = v;
+    }
+    for (int c = tid; c < nc; c += 256) {
+        const int64_t col = cb0 + c;
+        ofs_c[c] = col < N ? sc.fg[col] : -1;
+    }
+}
+
+// Fused store of one wave's tile (WR rows, BJ slices of CW complex columns),
+// staged through LDS: stage(j) writes slice j into stg (row stride SLD
+// reals), then each lane stores whole complex values V in the order in
+// which the target is contiguous (rows when mfast, else columns).  ofs_r
+// and ofs_c (fused_offsets, in LDS) start at the wave's first row and first
+// complex column.  64 is a multiple of WR and of CW, so a lane keeps one row
+// (row order) or one column (column order) across its stores.
 template <typename V, int WR, int CW, int SLD, int BJ, typename R, typename Stage>
-__device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, const ScatterStore &sc,
-                                                 int64_t row0, int64_t rbase, int64_t M, int cbase0,
-                                                 int Nr, int lane, Stage stage) {
+__device__ __forceinline__ void fused_store_wave(R *__restrict__ C, R *stg, int mfast, const int64_t *ofs_r,
+                                                 const int64_t *ofs_c, int lane, Stage stage) {
     static_assert(64 % WR == 0 && 64 % CW == 0, "lane-invariant row or column");
     constexpr int PER = WR * CW / 64;   // stores per lane and slice
-    const int64_t mask = ((int64_t)1 << sc.shift) - 1;
-    auto rowofs = [&](int lr) -> int64_t {
-        const int64_t row = rbase + lr;
-        if (row >= M) return -1;
-        const int64_t gr = row0 + row;
-        return sc.fa[gr >> sc.shift] + sc.fb[gr & mask];
-    };
-    if (sc.mfast) {
+    if (mfast) {
         const int lr = lane % WR;
-        const int64_t ro = rowofs(lr);
+        const int64_t ro = ofs_r[lr];
 #pragma unroll
         for (int j = 0; j < BJ; ++j) {
             stage(j);
             wave_sync();
-            const int cb = cbase0 + j * 2 * CW;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int lc = lane / WR + k * (64 / WR);
-                const int col = cb + 2 * lc;
-                if (ro >= 0 && col < Nr)
-                    *reinterpret_cast<V *>(C + 2 * (ro + sc.fg[col >> 1])) =
-                        *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
+                const int64_t co = ofs_c[j * CW + lc];
+                if (ro >= 0 && co >= 0)
+                    *reinterpret_cast<V *>(C + 2 * (ro + co)) = *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
             }
             wave_sync();
         }
     } else {
         const int lc = lane % CW;
-        int64_t ro[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) ro[k] = rowofs(lane / CW + k * (64 / CW));
 #pragma unroll
         for (int j = 0; j < BJ; ++j) {
             stage(j);
             wave_sync();
-            const int col = cbase0 + j * 2 * CW + 2 * lc;
-            const int64_t co = col < Nr ? sc.fg[col >> 1] : -1;
+            const int64_t co = ofs_c[j * CW + lc];
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int lr = lane / CW + k * (64 / CW);
-                if (ro[k] >= 0 && co >= 0)
-                    *reinterpret_cast<V *>(C + 2 * (ro[k] + co)) = *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
+                const int64_t ro = ofs_r[lr];
+                if (ro >= 0 && co >= 0)
+                    *reinterpret_cast<V *>(C + 2 * (ro + co)) = *reinterpret_cast<const V *>(&stg[lr * SLD + 2 * lc]);
             }
             wave_sync();
         }
@@ -361,6 +387,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     // its output through all of it after the k-loop)
     constexpr int SMEM = NSTAGE * NSPLIT * (APART + BPART);
     __shared__ ET smem[SMEM];
+    __shared__ int64_t fofs[SCAT ? BM + BN / 2 : 1];   // fused-store offsets: rows, then complex columns
     auto As = [&](int st) { return smem + st * NSPLIT * APART; };
     auto Bs = [&](int st) { return smem + NSTAGE * NSPLIT * APART + st * NSPLIT * BPART; };
     // a k-tile row is BK/4 float4; 256 threads cover RPP rows per pass;
@@ -379,6 +406,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
     C += u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
+    if constexpr (SCAT) fused_offsets(fofs, BM, fofs + BM, BN / 2, sc, row0, m0, M, n0 / 2, Nr / 2, tid);
     v16f acc[BI][BJ];
 #pragma unroll
     for (int i = 0; i < BI; ++i)
@@ -565,7 +593,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
         static_assert(4 * WR * SLD * sizeof(float) <= SMEM * sizeof(ET), "staging fits in the stages");
         float *stg = reinterpret_cast<float *>(smem) + wave * WR * SLD;
         fused_store_wave<float2, WR, CW, SLD, BJ>(
-            C, stg, sc, row0, m0 + wm * WR, M, n0 + wn * BJ * 32, Nr, lane, [&](int j) {
+            C, stg, sc.mfast, fofs + wm * WR, fofs + BM + wn * BJ * 16, lane, [&](int j) {
 #pragma unroll
                 for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -600,6 +628,7 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
     constexpr int BI = 2, BM = 128, BN = 64 * BJ, LD = M3_LD;
     constexpr int APL = BM * LD, BPL = BN * LD, STG = 2 * (APL + BPL);
     __shared__ float smem[2 * STG];
+    __shared__ int64_t fofs[SCAT ? BM + BN : 1];   // fused-store offsets: rows, then columns
     auto As = [&](int st, int p) { return smem + st * STG + p * APL; };
     auto Bs = [&](int st, int p) { return smem + st * STG + 2 * APL + p * BPL; };
     // a row's k-tile is 8 complex = 4 float4; 256 threads cover 64 rows per pass
@@ -614,6 +643,7 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
     C += 2 * u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    if constexpr (SCAT) fused_offsets(fofs, BM, fofs + BM, BN, sc, row0, m0, M, n0, N, tid);
     v16f acc[3][BI][BJ];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -750,7 +780,7 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
         float *stg = smem + wave * WR * SLD;
         const int hc = lane & 31, half = hc >> 4;
         fused_store_wave<float2, WR, 16, SLD, 2 * BJ>(
-            C, stg, sc, row0, m0 + wm * WR, M, 2 * (n0 + wn * BJ * 32), 2 * N, lane, [&](int s) {
+            C, stg, sc.mfast, fofs + wm * WR, fofs + BM + wn * BJ * 32, lane, [&](int s) {
                 if (half != (s & 1)) return;
                 const int jb = s >> 1;
 #pragma unroll
@@ -767,6 +797,153 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
                         }
                 }
             });
+    }
+}
+
+// The three-multiplication form for short K (even K <= 32 complex): steps
+// whose output is many times their operands (K = 16 or 32 against N of
+// hundreds to thousands), so that the time goes to writing the output.  A
+// block owns 128 rows (32 per wave) and a chunk of S3_NT column tiles of 32
+// complex; each wave keeps the re, im and (re + im) fragments of its rows,
+// all of K, in registers for the whole chunk, and the block walks the column
+// tiles with the next tile's B loaded during the current one's MFMAs (two
+// LDS stages of re and im planes, one barrier per tile).  Each tile's
+// product is stored as soon as it is formed, so the stores of one tile drain
+// while the MFMAs of the next run (and while other waves on the SIMD
+// compute).  G k-groups of 8 complex cover K (a tail group is zero-filled).
+constexpr int S3_NT = 8;
+template <bool SCAT, int G>
+__global__ __launch_bounds__(256, SCAT || G > 2 ? 3 : 4) void k_gemm_3m_short(const float *__restrict__ A,
+                                                                       const float *__restrict__ B,
+                                                                       float *__restrict__ C, int64_t M, int K, int N,
+                                                                       int64_t sA, int64_t sB, int64_t sC, int chunks_n,
+                                                                       ScatterStore sc, int64_t row0) {
+    constexpr int KP = 8 * G;          // k (complex) covered by the groups
+    constexpr int BLD = KP + 4;        // floats per plane row: 16-byte aligned, rows on distinct banks
+    constexpr int BPL = 32 * BLD;      // one plane of one stage
+    constexpr int WR = 32, SLD = 34;   // output staging of a wave: 32 rows of 32 floats + 2
+    constexpr int NF4 = 16 * KP;       // float4 (two complex) in one B tile
+    constexpr int PB = (NF4 + 255) / 256;
+    __shared__ float bs[2 * 2 * BPL];  // [stage][plane re / im]
+    __shared__ float stg_all[4 * WR * SLD];
+    __shared__ int64_t fofs[SCAT ? 128 + 32 * S3_NT : 1];   // fused-store offsets: rows, then columns
+    const int64_t u = blockIdx.y;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tm = tile / chunks_n, tc = tile - tm * chunks_n;
+    const int64_t m0 = tm * 128;
+    const int c0 = (int)tc * (32 * S3_NT);
+    const int ntile = min(S3_NT, (N - c0 + 31) / 32);
+    A += 2 * u * sA;
+    B += 2 * u * sB;
+    C += 2 * u * sC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, slot = lane >> 5;
+    if constexpr (SCAT) fused_offsets(fofs, 128, fofs + 128, 32 * S3_NT, sc, row0, m0, M, c0, N, tid);
+    // A fragments: lane (r, slot) holds k = 8 g + 4 slot + t (t = 0..3) of
+    // row m0 + 32 wave + r, the k of the t-th MFMA of group g; rows past M
+    // read the last row (never stored), k past K reads zero.  The (re + im)
+    // fragments are formed per tile (four adds against twelve MFMAs), which
+    // keeps the kernel at three waves per SIMD.
+    v4f ar[G], ai[G];
+    {
+        const float *ap = A + 2 * std::min<int64_t>(m0 + 32 * wave + r, M - 1) * K;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = 8 * g + 4 * slot;
+            v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = v4f{0.f, 0.f, 0.f, 0.f};
+            if (k + 2 <= K) x0 = *reinterpret_cast<const v4f *>(ap + 2 * k);
+            if (k + 4 <= K) x1 = *reinterpret_cast<const v4f *>(ap + 2 * k + 4);
+            ar[g] = v4f{x0[0], x0[2], x1[0], x1[2]};
+            ai[g] = v4f{x0[1], x0[3], x1[1], x1[3]};
+        }
+    }
+    // B tile j: columns c0 + 32 j .. + 31, float4 f = column (f / (KP/2)),
+    // complex pair (f % (KP/2)); columns past N read the last column
+    v4f rb[PB];
+    auto fetch = [&](int j) {
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int f = tid + 256 * i;
+            const int cc = f / (KP / 2), k = 2 * (f % (KP / 2));
+            const int col = std::min(c0 + 32 * j + cc, N - 1);
+            rb[i] = (f < NF4 && k < K) ? *reinterpret_cast<const v4f *>(B + 2 * ((int64_t)col * K + k))
+                                       : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int f = tid + 256 * i;
+            if (f >= NF4) continue;
+            const int cc = f / (KP / 2), k = 2 * (f % (KP / 2));
+            float *p0 = bs + st * 2 * BPL + cc * BLD + k;
+            *reinterpret_cast<v2f *>(p0) = v2f{rb[i][0], rb[i][2]};
+            *reinterpret_cast<v2f *>(p0 + BPL) = v2f{rb[i][1], rb[i][3]};
+        }
+    };
+    float *stg = stg_all + wave * WR * SLD;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int j = 0; j < ntile; ++j) {
+        const int st = j & 1;
+        if (j + 1 < ntile) fetch(j + 1);
+        v16f t0, t1, t2;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) t0[e] = t1[e] = t2[e] = 0.0f;
+        const float *bre = bs + st * 2 * BPL + r * BLD + 4 * slot;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const v4f br = *reinterpret_cast<const v4f *>(bre + 8 * g);
+            const v4f bi = *reinterpret_cast<const v4f *>(bre + BPL + 8 * g);
+            const v4f bsum = br + bi, asum = ar[g] + ai[g];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                t0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[g][t], br[t], t0, 0, 0, 0);
+                t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[g][t], bi[t], t1, 0, 0, 0);
+                t2 = __builtin_amdgcn_mfma_f32_32x32x2f32(asum[t], bsum[t], t2, 0, 0, 0);
+            }
+        }
+        if (j + 1 < ntile) stash(st ^ 1);
+        // Re = T0 - T1 into t0, Im = T2 - T0 - T1 into t1 (t2 is then free)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float a = t0[e], b = t1[e];
+            t0[e] = a - b;
+            t1[e] = t2[e] - a - b;
+        }
+        const int cj = c0 + 32 * j;
+        // accumulator layout: lane holds complex column cj + r and rows
+        // 8 (e / 4) + 4 slot + e % 4 of the wave's 32
+        if constexpr (!SCAT) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t row = m0 + 32 * wave + 8 * (e >> 2) + 4 * slot + (e & 3);
+                const int col = cj + r;
+                if (row < M && col < N) *reinterpret_cast<v2f *>(C + 2 * (row * N + col)) = v2f{t0[e], t1[e]};
+            }
+        } else if (!sc.mfast) {
+            // columns contiguous in the target: the accumulator layout is
+            // already in store order (32 lanes, 32 consecutive columns of a
+            // row), so the values go out directly, offsets read from LDS
+            const int64_t co = fofs[128 + 32 * j + r];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t ro = fofs[32 * wave + 8 * (e >> 2) + 4 * slot + (e & 3)];
+                if (ro >= 0 && co >= 0) *reinterpret_cast<v2f *>(C + 2 * (ro + co)) = v2f{t0[e], t1[e]};
+            }
+        } else {
+            const int half = r >> 4;
+            fused_store_wave<float2, WR, 16, SLD, 2>(
+                C, stg, sc.mfast, fofs + 32 * wave, fofs + 128 + 32 * j, lane, [&](int s) {
+                    if (half != s) return;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        *reinterpret_cast<v2f *>(&stg[(8 * (e >> 2) + 4 * slot + (e & 3)) * SLD + 2 * (r - 16 * s)]) =
+                            v2f{t0[e], t1[e]};
+                });
+        }
+        __syncthreads();
     }
 }
 
@@ -790,6 +967,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
     static_assert(BM % 64 == 0 && BN % 64 == 0, "tile edges are multiples of 64");
     __shared__ double As[NSTAGE][BM * F64_LD];
     __shared__ double Bs[NSTAGE][BN * F64_LD];
+    __shared__ int64_t fofs[SCAT ? BM + BN / 2 : 1];   // fused-store offsets: rows, then complex columns
     const int64_t u = blockIdx.y;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
@@ -800,6 +978,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
     C += u * sC;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    if constexpr (SCAT) fused_offsets(fofs, BM, fofs + BM, BN / 2, sc, row0, m0, M, n0 / 2, Nr / 2, tid);
     v4d acc[BI][BJ];
 #pragma unroll
     for (int i = 0; i < BI; ++i)
@@ -918,27 +1097,24 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A,
     } else {
         // fused store, direct: each lane already writes 8-byte values and the
         // re/im halves of a complex value sit in neighbouring lanes, so
-        // (measured) staging through LDS does not pay here; the row parts of
-        // the target offsets are looked up once per row, the column parts
-        // once per column block
+        // (measured) staging through LDS does not pay here; the offsets come
+        // from LDS (fused_offsets)
         int64_t cofs[BJ];
 #pragma unroll
         for (int j = 0; j < BJ; ++j) {
-            const int col = n0 + wn * BJ * 16 + j * 16 + (lane & 15);
-            cofs[j] = col < Nr ? 2 * sc.fg[col >> 1] + (col & 1) : -1;
+            const int col = wn * BJ * 16 + j * 16 + (lane & 15);   // within the block
+            const int64_t co = fofs[BM + (col >> 1)];
+            cofs[j] = co >= 0 ? 2 * co + (col & 1) : -1;
         }
-        const int64_t mask = ((int64_t)1 << sc.shift) - 1;
 #pragma unroll
         for (int i = 0; i < BI; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * BI * 16 + i * 16 + (lane >> 4) + 4 * r;
-                if (row >= M) continue;
-                const int64_t gr = row0 + row;
-                const int64_t rofs = 2 * (sc.fa[gr >> sc.shift] + sc.fb[gr & mask]);
+                const int64_t ro = fofs[wm * BI * 16 + i * 16 + (lane >> 4) + 4 * r];
+                if (ro < 0) continue;
 #pragma unroll
                 for (int j = 0; j < BJ; ++j)
-                    if (cofs[j] >= 0) C[rofs + cofs[j]] = acc[i][j][r];
+                    if (cofs[j] >= 0) C[2 * ro + cofs[j]] = acc[i][j][r];
             }
     }
 }
@@ -1022,6 +1198,9 @@ __global__ __launch_bounds__(256) void k_small_fixed(const R *__restrict__ A, co
     constexpr int LD = KK + 1;
     __shared__ C2 As[256 * LD];
     __shared__ C2 Bs[NN * KK];
+    // the column parts of the fused-store offsets, read once per block: a
+    // table read between two stores would wait for the stores in flight
+    __shared__ int64_t fgs[SCAT ? NN : 1];
     const int64_t u = blockIdx.y;
     const int64_t m0 = (int64_t)blockIdx.x * 256;
     const int rows = (int)(M - m0 < 256 ? M - m0 : 256);
@@ -1029,6 +1208,8 @@ __global__ __launch_bounds__(256) void k_small_fixed(const R *__restrict__ A, co
     const C2 *a = reinterpret_cast<const C2 *>(A) + u * sA + m0 * KK;
     const C2 *b = reinterpret_cast<const C2 *>(Bt) + u * sB;
     for (int i = tid; i < NN * KK; i += 256) Bs[i] = b[i];
+    if constexpr (SCAT)
+        if (tid < NN) fgs[tid] = sc.fg[tid];
     if constexpr (sizeof(R) == 4 && KK % 2 == 0) {
         // two complex64 values per 16-byte load (the chunk starts 16-byte aligned)
         const float4 *a4 = reinterpret_cast<const float4 *>(a);
@@ -1066,7 +1247,7 @@ __global__ __launch_bounds__(256) void k_small_fixed(const R *__restrict__ A, co
         C2 v;
         v.x = re;
         v.y = im;
-        if constexpr (SCAT) c[base + sc.fg[n]] = v;
+        if constexpr (SCAT) c[base + fgs[n]] = v;
         else c[base + n] = v;
     }
 }
@@ -1295,6 +1476,20 @@ void gather(const void *in, void *out, int64_t units, int64_t in_unit_stride,
     check_launch("gather");
 }
 
+void expand_prefix(const void *pre, void *out, int64_t units, int64_t u0, int64_t nper, int64_t elems,
+                   int64_t out_us, int elem_bytes, void *stream) {
+    const int64_t total = units * elems;
+    if (total <= 0) return;
+    const dim3 grid(grid_for(total, 256));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL((k_expand_prefix<float2>), grid, dim3(256), 0, (hipStream_t)stream,
+                           (const float2 *)pre, (float2 *)out, units, u0, nper, elems, out_us);
+    else
+        hipLaunchKernelGGL((k_expand_prefix<double2>), grid, dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)pre, (double2 *)out, units, u0, nper, elems, out_us);
+    check_launch("expand_prefix");
+}
+
 void gather_site(const void *site, void *out, int64_t units, int64_t u0, int64_t n_slices,
                  int64_t slice0, int64_t site_stride, const SliceMap &sm, int64_t out_unit_stride,
                  const Gather &g, int elem_bytes, void *stream) {
@@ -1427,18 +1622,50 @@ void launch_3m(const float *A, const float *Bt, float *C, int64_t units, int64_t
     }
 }
 
+template <int G>
+void launch_3m_short(const float *A, const float *Bt, float *C, int64_t units, int64_t M, int64_t K, int64_t N,
+                     int64_t sA, int64_t sB, int64_t sC, hipStream_t st, const ScatterStore *sc) {
+    const int chunks_n = (int)((N + 32 * S3_NT - 1) / (32 * S3_NT));
+    const int64_t rows_per = (((int64_t)1 << 30) / chunks_n) * 128;
+    const ScatterStore none{};
+    for (int64_t u0 = 0; u0 < units; u0 += 65535) {
+        const int64_t nu = std::min<int64_t>(65535, units - u0);
+        for (int64_t r0 = 0; r0 < M; r0 += rows_per) {
+            const int64_t mr = std::min<int64_t>(rows_per, M - r0);
+            const dim3 grid((unsigned)(((mr + 127) / 128) * chunks_n), (unsigned)nu);
+            const int64_t crow = sc ? 0 : r0;
+            const float *a = A + 2 * (u0 * sA + r0 * K);
+            const float *b = Bt + 2 * u0 * sB;
+            float *c = C + 2 * (u0 * sC + crow * N);
+            if (sc)
+                hipLaunchKernelGGL((k_gemm_3m_short<true, G>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, chunks_n, *sc, r0);
+            else
+                hipLaunchKernelGGL((k_gemm_3m_short<false, G>), grid, dim3(256), 0, st, a, b, c, mr, (int)K, (int)N,
+                                   sA, sB, sC, chunks_n, none, (int64_t)0);
+            check_launch("gemm_3m_short");
+        }
+    }
+}
+
 void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int64_t K,
           int64_t N, int64_t sA, int64_t sB, int64_t sC, int mode, void *stream,
           const ScatterStore *sc) {
     // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
     // split-BF16 MFMA with 3 / 6 products, 4 complex64 in the three-
     // multiplication form (FP32 MFMA; Bt is then the plain complex [N][K], not
-    // its real embedding).  Strides arrive in complex elements; the kernels
-    // index reals.
+    // its real embedding; K <= 32 takes the short-K kernel).  Strides arrive
+    // in complex elements; the kernels index reals.
     const hipStream_t st = (hipStream_t)stream;
     if (mode == 4) {
         if (K % 2 != 0) fail(TNS_E_UNSUPPORTED, "three-multiplication GEMM needs an even K");
         if (units <= 0 || M <= 0 || N <= 0) return;
+        if (K <= 32) {
+            // short K: the output dominates (K = 16: 2 groups of 8, K = 32: 4)
+            if (K <= 16) launch_3m_short<2>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
+            else launch_3m_short<4>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
+            return;
+        }
         // BJ = 2 (128 x 128 complex, one wave per SIMD) measured level with or
         // up to 10 % behind BJ = 1 (two waves per SIMD) on every step shape
         launch_3m<1>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);

@@ -1085,6 +1085,38 @@ static void compile_steps(Plan &p) {
         }
         div *= p.bond_overlap[e];
     }
+
+    // Slice prefix.  Cutting turns the network into sub-networks that differ
+    // only in the indices of the cut bonds, so the pairwise steps before the
+    // first tensor that carries a cut bond are the same in every one of them.
+    // The leading main-path steps that absorb uncut sites form the prefix,
+    // computed once per bitstring; it must end before the last step and hold
+    // at least one contraction besides the start.
+    p.prefix_steps = 0;
+    p.prefix_elems = 0;
+    p.prefix_flops = 0;
+    if (p.n_slices > 1) {
+        int P = 0;
+        for (size_t m = 0; m + 1 < p.steps.size(); ++m) {
+            const Step &s = p.steps[m];
+            if (s.chain != 0 || s.branch >= 0 || p.slice_map[s.site].n > 0) break;
+            P = (int)m + 1;
+        }
+        if (P >= 2) {
+            double fl = 0, by = 0;
+            for (int m = 0; m < P; ++m) {
+                const Step &s = p.steps[m];
+                if (s.start) continue;
+                fl += 8.0 * (double)s.M * s.K * s.N;
+                by += elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
+            }
+            p.prefix_steps = P;
+            p.prefix_elems = p.steps[P - 1].out_elems;
+            p.prefix_flops = fl;
+            p.flops_per_amp -= (ns - 1) * fl;
+            p.gemm_bytes_per_amp -= (ns - 1) * by;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------

@@ -235,14 +235,32 @@ void plan_device_release(Plan &p) {
 // ----------------------------------------------------------------------------
 // executor
 
-int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget) {
+int64_t max_bitstrings_per_batch(const Ctx *, const Plan &p, uint64_t budget, int64_t n_sl) {
     // half of the budget for per-bitstring tensors, the rest for work units
     int64_t per = p.bytes_per_bitstring + p.n_slices * 16 * p.out_per_unit + 32;
     int64_t nb = (int64_t)(budget / 2) / std::max<int64_t>(per, 1);
-    return std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+    nb = std::max<int64_t>(1, std::min<int64_t>(nb, 4096));
+    // a shared slice prefix: as many bitstrings as an eighth of the budget
+    // holds prefix tensors for (none fits: the prefix is recomputed per unit)
+    if (p.prefix_steps > 0 && n_sl > 1) {
+        const int64_t pb = p.prefix_elems * (p.precision != TNS_C128 ? 8 : 16);
+        const int64_t cap = (int64_t)(budget / 8) / std::max<int64_t>(pb, 1);
+        if (cap >= 1) nb = std::min(nb, cap);
+    }
+    return nb;
 }
 
-enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_TZ, S_COUNT };
+enum Slot { S_BITS = 0, S_BRA, S_VP, S_SITES, S_PARTIAL, S_AMPS, S_TX, S_TY, S_B, S_TZ, S_PRE, S_COUNT };
+
+// The slice prefix is shared when several slices of a bitstring run in the
+// call and the batch's prefix tensors take at most an eighth of the budget
+// (a prefix as large as the biggest intermediates -- 2^32 elements at 104
+// qubits -- is recomputed per unit instead of holding a third boundary-sized
+// buffer).
+static bool share_prefix(const Plan &p, int64_t nb, int64_t n_sl, uint64_t budget) {
+    const int64_t elem = p.precision != TNS_C128 ? 8 : 16;
+    return p.prefix_steps > 0 && n_sl > 1 && (uint64_t)(nb * p.prefix_elems * elem) <= budget / 8;
+}
 
 uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t budget) {
     // mirrors the slot sizes run_amplitudes takes from a fresh workspace
@@ -251,17 +269,19 @@ uint64_t call_workspace_bytes(const Plan &p, int64_t n, int64_t n_sl, uint64_t b
     const Circuit &c = p.circ;
     const int64_t elem = p.precision != TNS_C128 ? 8 : 16;
     const int64_t opu = p.out_per_unit;
-    auto slot = [](int64_t b) { return (uint64_t)std::max<int64_t>(b, 256); };
+    // the arena rounds every slot up to 256 bytes
+    auto slot = [](int64_t b) { return ((uint64_t)std::max<int64_t>(b, 256) + 255) & ~(uint64_t)255; };
     int64_t bra_total = 0, site_total = 0;
     for (int q = 0; q < c.n; ++q) {
         bra_total += 2 * p.bra.cap[q];
         site_total += p.site_elems[q];
     }
-    const int64_t nb = std::min<int64_t>(n, max_bitstrings_per_batch(nullptr, p, budget));
+    const int64_t nb = std::min<int64_t>(n, max_bitstrings_per_batch(nullptr, p, budget, n_sl));
     const int64_t units = nb * n_sl;
     uint64_t used = slot(n * opu * 16) + slot(nb * c.n) + slot(bra_total * nb * 16) +
                     slot(std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16) +
                     slot(site_total * nb * elem) + slot(units * opu * 16);
+    if (share_prefix(p, nb, n_sl, budget)) used += slot(nb * p.prefix_elems * elem);
     const uint64_t left = budget > used ? budget - used : 0;
     int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
     const int64_t fill = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max<int64_t>(p.unit_stride, 1));
@@ -306,7 +326,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
     const int64_t n_sl = slice_end - slice_begin;   // slices computed per bitstring
     const bool c64 = p.precision != TNS_C128;
     const int elem = c64 ? 8 : 16;
-    const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget));
+    const int64_t nb_max = std::min<int64_t>(n, max_bitstrings_per_batch(ctx, p, budget, n_sl));
     // phase timing syncs the host on events: only when stats are asked for
     const bool timing = st.profile;
 
@@ -331,6 +351,9 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         double *vp = (double *)ws.get(ctx, S_VP, (size_t)std::max<int64_t>(p.bra_scratch_elems, 1) * nb * 16, stream);
         char *sites = (char *)ws.get(ctx, S_SITES, (size_t)site_total * nb * elem, stream);
         double *partial = (double *)ws.get(ctx, S_PARTIAL, (size_t)units * opu * 16, stream);
+        // slice prefix: computed once per bitstring when several slices run
+        const bool share = share_prefix(p, nb, n_sl, budget);
+        char *pre = share ? (char *)ws.get(ctx, S_PRE, (size_t)nb * p.prefix_elems * elem, stream) : nullptr;
         const uint64_t used = ws.bytes;
         const uint64_t left = budget > used ? budget - used : 0;
         int64_t G = (int64_t)(left / std::max<int64_t>(p.bytes_per_unit, 1));
@@ -405,24 +428,26 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
             if (!st.profile) return;
             (void)hipEventRecord(evs.back().b, (hipStream_t)stream);
         };
-        for (int64_t ug0 = 0; ug0 < units; ug0 += G) {
-            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
-            const int64_t g = std::min(G, units - ug0);
-            // Boundary buffers: X and Y hold the main path's tensor (ping-pong);
-            // a branch's tensors alternate between Z and whichever of X / Y
-            // the main path is not using.  An absorbed branch tensor is first
-            // copied into the B operand, so its buffer is free again before
-            // the step's permute and GEMM write.
-            struct Buf { char *p; int64_t us; };
-            const Buf bx{X, peak}, by{Y, peak}, bz{Z, p.branch_stride};
-            Buf cur_main{nullptr, 0}, cur_br{nullptr, 0};
+        // Boundary buffers: X and Y hold the main path's tensor (ping-pong);
+        // a branch's tensors alternate between Z and whichever of X / Y the
+        // main path is not using.  An absorbed branch tensor is first copied
+        // into the B operand, so its buffer is free again before the step's
+        // permute and GEMM write.
+        struct Buf { char *p; int64_t us; };
+        const Buf bx{X, peak}, by{Y, peak}, bz{Z, p.branch_stride};
+        // Steps [m0, m1) on g units: unit u is bitstring (u0 + u) / nper of
+        // the batch and slice s0 + (u0 + u) % nper; cur_main holds the main
+        // tensor when m0 > 0; last (if set) receives the output of step m1 - 1.
+        auto run_steps = [&](size_t m0, size_t m1, int64_t g, int64_t u0, int64_t nper, int64_t s0,
+                             Buf cur_main, const Buf *last) {
+            Buf cur_br{nullptr, 0};
             auto free_main = [&]() { return cur_main.p == X ? by : bx; };
-            for (size_t m = 0; m < p.steps.size(); ++m) {
+            for (size_t m = m0; m < m1; ++m) {
                 const Step &s = p.steps[m];
                 const bool main = s.chain == 0;
                 if (s.start) {
                     const Buf to = main ? bx : bz;
-                    launch::gather_site(site_ptr[s.site], to.p, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
+                    launch::gather_site(site_ptr[s.site], to.p, g, u0, nper, s0, p.site_elems[s.site],
                                         p.slice_map[s.site], to.us, s.bgather, elem, stream);
                     (main ? cur_main : cur_br) = to;
                     st.launches += 1;
@@ -432,7 +457,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 // real embedding, the three-multiplication GEMM and the small kernels
                 // the plain complex matrix
                 if (s.branch < 0)
-                    launch::build_b(site_ptr[s.site], Bb, g, ug0, n_sl, slice_begin, p.site_elems[s.site],
+                    launch::build_b(site_ptr[s.site], Bb, g, u0, nper, s0, p.site_elems[s.site],
                                     p.slice_map[s.site], s.bgather, s.K, s.N, c64 ? 1 : 0,
                                     s.kernel == 0 ? 1 : 0, stream);
                 else
@@ -454,16 +479,17 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     src = o;
                     st.launches += 1;
                 }
-                const Buf dst = other_of(src);
+                const Buf dst = (last && m + 1 == m1) ? *last : other_of(src);
                 const double mkn = (double)s.M * s.K * s.N * g;
                 const double bytes = (double)elem * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N) * g;
                 const bool is_gemm = s.kernel == 0 || s.kernel == 3;
                 // real flops the MFMA instructions execute: 8 M K N for the real
                 // embedding, 6 M K N for the three-multiplication form, times the
-                // number of products of a split-BF16 form
+                // number of products of a split-BF16 form; class 3 is k_gemm_3m
+                // (the short-K steps of the same form count with the other GEMMs)
                 const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
                                     : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
-                ev_begin(s.kernel == 3 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
+                ev_begin(s.kernel == 3 && s.K > 32 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
                          (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
                     launch::gemm(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us, p.precision,
@@ -475,17 +501,37 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                     launch::small_contract(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us,
                                            c64 ? 1 : 0, stream, s.store_fused ? &p.scatter[m] : nullptr);
                 else
-                    launch::final_dot(src.p, Bb, partial + 2 * ug0, g, s.K, src.us, s.K, c64 ? 1 : 0, stream);
+                    launch::final_dot(src.p, Bb, partial + 2 * u0, g, s.K, src.us, s.K, c64 ? 1 : 0, stream);
                 ev_end();
                 if (m + 1 == p.steps.size() && s.kernel != 2) {
                     // open legs: the last tensor holds this unit's 2^open values
-                    launch::finalize(dst.p, partial + 2 * ug0 * opu, g, dst.us, opu, p.final_perm,
+                    launch::finalize(dst.p, partial + 2 * u0 * opu, g, dst.us, opu, p.final_perm,
                                      c64 ? 1 : 0, stream);
                     st.launches += 1;
                 }
                 st.launches += 2;
                 (main ? cur_main : cur_br) = dst;
             }
+        };
+        // the slice prefix, once per bitstring of the batch (G at a time)
+        const size_t P = share ? (size_t)p.prefix_steps : 0;
+        for (int64_t pb0 = 0; share && pb0 < nb; pb0 += G) {
+            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+            const int64_t g = std::min(G, nb - pb0);
+            const Buf out{pre + (size_t)pb0 * p.prefix_elems * elem, p.prefix_elems};
+            run_steps(0, P, g, pb0, 1, 0, Buf{nullptr, 0}, &out);
+        }
+        for (int64_t ug0 = 0; ug0 < units; ug0 += G) {
+            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+            const int64_t g = std::min(G, units - ug0);
+            Buf start{nullptr, 0};
+            if (share) {
+                // every unit starts from its bitstring's prefix tensor
+                launch::expand_prefix(pre, X, g, ug0, n_sl, p.prefix_elems, peak, elem, stream);
+                st.launches += 1;
+                start = bx;
+            }
+            run_steps(P, p.steps.size(), g, ug0, n_sl, slice_begin, start, nullptr);
         }
         launch::slice_sum(partial, amps_dev + 2 * b0 * opu, nb, n_sl, opu, stream);
         st.launches += 1;

@@ -225,6 +225,33 @@ def test_explicit_cuts_multiply_slices(ctx):
     assert list(i1.cut_edges) == [3, 10]
 
 
+def test_slice_prefix_accounting(ctx):
+    # cutting leaves the sub-networks different only in the cut indices, so
+    # the steps before the first site that carries a cut bond are the same in
+    # every slice: the plan reports them as a prefix counted once per
+    # bitstring.  On a linear path the start site is order[0] and step j
+    # absorbs order[j + 1], so the prefix holds the t - 1 steps before the
+    # first cut site at position t (none when t < 2: the start alone is not
+    # shared).
+    c, _ = config("grid5x5_d10")
+    order = [int(x) for x in ctx.plan(c, precision="c64").info().path]
+    edges = [tuple(map(int, e)) for e in c.edges]
+    seen = set()
+    for e, (a, b) in enumerate(edges):
+        t = min(order.index(a), order.index(b))
+        if t in seen and t not in (0, 1):
+            continue
+        seen.add(t)
+        i = ctx.plan(c, precision="c64", cuts=[e], path=order, branches=False).info()
+        want = t - 1 if t >= 2 else 0
+        assert i.n_prefix_steps == want, (a, b, t)
+        mkn = 8 * i.step_m.astype(float) * i.step_k * i.step_n
+        assert i.prefix_flops_per_amp == pytest.approx(np.sum(mkn[:want]))
+        ns = i.n_slices
+        assert ns == i.bond_overlap[e] and ns > 1
+        assert i.flops_per_amp == pytest.approx(ns * np.sum(mkn) - (ns - 1) * np.sum(mkn[:want]))
+
+
 def test_automatic_cuts_respect_limit(ctx):
     c, _ = config("grid5x5_d10")
     i = ctx.plan(c, precision="c64", max_intermediate_elems=1 << 18).info()

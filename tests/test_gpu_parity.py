@@ -106,6 +106,33 @@ def test_slice_ranges_add_up(ctx, small):
         ctx.amplitudes(p, bits, slices=(5, 5))
 
 
+def late_cuts(c, order, k):
+    """Up to k bonds whose sites both sit in the last four places of order."""
+    edges = [tuple(map(int, e)) for e in c.edges]
+    late = [e for e, (a, b) in enumerate(edges) if min(order.index(a), order.index(b)) >= c.n - 4]
+    return late[:k]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_slice_prefix_shared(ctx, small, prec):
+    # cut bonds between the last sites of the order: every slice shares the
+    # steps before them, which run once per bitstring and are copied to each
+    # (bitstring, slice) unit.  Amplitudes against the oracle; a range of one
+    # slice (computed without sharing) plus the others (shared) is the whole.
+    c, bits, ref = small
+    order = [int(x) for x in ctx.plan(c, split_cycle=4, precision=prec).info().path]
+    cuts = late_cuts(c, order, 2)
+    p = ctx.plan(c, split_cycle=4, precision=prec, cuts=cuts, path=order, branches=False)
+    i = p.info()
+    say("grid3x4_d8 prefix", prec, "cuts", cuts, "prefix steps", i.n_prefix_steps, "of", len(i.step_m),
+        "slices", i.n_slices)
+    assert i.n_prefix_steps >= c.n - 5 and i.n_slices > 1
+    got = ctx.amplitudes(p, bits)
+    check(ref, got, c.n, prec)
+    parts = [ctx.amplitudes(p, bits, slices=r) for r in ((0, 1), (1, 7), (7, i.n_slices))]
+    assert compare(got, sum(parts), c.n)["rel_l2"] <= (1e-13 if prec == "c128" else 1e-6)
+
+
 def fill_open(bits, open_qubits):
     """All bitstrings of each row with its open bits set to x = 0..2^k-1
     (first open qubit most significant)."""
@@ -202,6 +229,20 @@ def _row_kernel_steps(info, csize):
             rows.append(t)
     fused = [t for t in rows if t + 1 < len(k) and sp[t + 1] == 2]
     return rows, fused
+
+
+def test_slice_prefix_grid5x5_d10(ctx, grid5x5_d10_ref):
+    # the 25-qubit batch with one cut bond absorbed half-way along the path
+    # (sites 13 and 18): the first twelve steps are shared by the slices
+    c, bits, ref = grid5x5_d10_ref
+    order = [int(x) for x in ctx.plan(c, precision="c64").info().path]
+    edges = [tuple(map(int, e)) for e in c.edges]
+    p = ctx.plan(c, precision="c64", cuts=[edges.index((13, 18))], path=order, branches=False)
+    i = p.info()
+    say("grid5x5_d10 prefix steps", i.n_prefix_steps, "slices", i.n_slices)
+    assert i.n_prefix_steps > 0
+    got = ctx.amplitudes(p, bits)
+    check(ref, got, c.n, "c64")
 
 
 @pytest.fixture(scope="module")
