@@ -51,6 +51,29 @@ def test_noalloc_matches_amplitudes(prec, open_qubits):
         ctx.close()
 
 
+def test_noalloc_with_shared_slice_prefix():
+    # two cut bonds among the last sites of the path: the call keeps the
+    # slice prefix of each bitstring in the static workspace too
+    import torch
+    c, bits = config("grid3x4_d8")
+    ctx = T.Context(0)
+    try:
+        order = [int(x) for x in ctx.plan(c, split_cycle=4, precision="c64").info().path]
+        edges = [tuple(map(int, e)) for e in c.edges]
+        cuts = [e for e, (a, b) in enumerate(edges) if min(order.index(a), order.index(b)) >= c.n - 4][:2]
+        p = ctx.plan(c, split_cycle=4, precision="c64", cuts=cuts, path=order, branches=False)
+        assert p.info().n_prefix_steps > 0
+        for label, b in (("64 bitstrings", bits), ("16 others", bitstrings(12, 16, 7))):
+            say("noalloc prefix", label)
+            want = ctx.amplitudes(p, b).reshape(-1)
+            got = _noalloc(ctx, p, b, torch)
+            m = compare(want, got, c.n)
+            assert m["rel_l2"] <= TOL["c64"] and m["max_scaled"] <= 10 * TOL["c64"], m
+        p.close()
+    finally:
+        ctx.close()
+
+
 def test_noalloc_rejects_plans_beyond_the_static_workspace():
     import torch
     c, bits = config("grid5x5_d10", n_bits=1)
