@@ -108,7 +108,6 @@ struct Server {
     std::mutex m;
     std::condition_variable cv;
     std::list<Request *> active;
-    std::list<Request *>::iterator rr;
     bool stop = false;
     bool pressure = false;               // an item waits for memory
     uint64_t pool = 0;                   // bytes the workers share
@@ -129,7 +128,6 @@ struct Server {
             hip_check(hipStreamCreate(&s), "hipStreamCreate");
             streams[i] = s;
         }
-        rr = active.end();
         for (int i = 0; i < n_workers; ++i) workers.emplace_back([this, i] { loop(i); });
     }
 
@@ -229,10 +227,8 @@ struct Server {
         const bool over = r->running == 0 &&
                           (r->finished_items >= r->n_items || r->status != TNS_OK || r->cancel);
         if (!over) return;
-        // step the round-robin cursor off r before its node is erased
         auto it = std::find(active.begin(), active.end(), r);
         if (it == active.end()) return;   // already completed
-        if (rr == it) ++rr;
         active.erase(it);
         r->plan->serving_in_flight--;
         cv.notify_all();   // a tns_plan_destroy may wait for this plan's requests

@@ -62,6 +62,26 @@ def test_sliced_requests_in_single_units(g12):
         ctx.close()
 
 
+def test_many_short_requests_freed_at_once(g12):
+    # each request is freed the moment its wait returns, while the workers
+    # still complete and notify the others: the request must not be touched
+    # after the waiter has seen it done
+    c, bits, ref = g12
+    ctx = T.Context(0)
+    try:
+        p = ctx.plan(c, precision="c64")
+        alone = ctx.amplitudes(p, bits[:4])
+        say("64 short requests, freed as they finish")
+        reqs = [ctx.submit(p, bits[:4]) for _ in range(64)]
+        for r in reqs:
+            got = r.wait().copy()
+            r.close()
+            assert np.array_equal(got, alone)
+        p.close()
+    finally:
+        ctx.close()
+
+
 def test_two_requests_run_together():
     # two requests submitted together run concurrently: each one's run
     # interval (admission to completion) overlaps the other's
