@@ -34,12 +34,11 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# dense MFMA peaks of MI355X: FP32, FP64; split-BF16 GEMMs are priced against
-# the FP32 peak for the same algorithmic (complex64) flops
-# dense MFMA peaks: FP32 for complex64, FP64 for complex128; the split-BF16
-# forms are priced at the FP32 peak for the same algorithmic flops (their
-# executed BF16 rate is reported beside it)
-PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "c64_bf16x3": 157.3, "c64_bf16x6": 157.3}
+# dense MFMA peaks of MI355X (TFLOP/s): FP32 for complex64, FP64 for
+# complex128, BF16 for the split-BF16 forms, whose BF16 products are the
+# executed flops (the complex product's 8 M K N count is reported beside it
+# as credited_tflops)
+PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6, "c64_bf16x3": 2500.0, "c64_bf16x6": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel (k_gemm_3m), from rocprofv3
@@ -414,16 +413,16 @@ def gemm_roofline(agg, precision, workload):
     if not n or not ms:
         return None
     peak = PEAK_TFLOPS[precision]
-    bf16 = precision.startswith("c64_bf16")
-    # split-BF16: priced at the FP32 peak for the complex product's flops
-    achieved = (cr if bf16 else ex) / (ms * 1e-3) / 1e12
+    # executed MFMA flops over the peak of the instructions that run them
+    # (split-BF16: 3 or 6 BF16 products per real product, dense BF16 peak)
+    achieved = ex / (ms * 1e-3) / 1e12
     alg_launch = by / n
     src_hash = kernel_source_hash()
     traffic = measured_traffic(src_hash, workload, alg_launch / 2 ** 20) if precision == "c64" else None
     return {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "launches": int(n), "avg_launch_ms": round(ms / n, 4),
-            "flops_per_launch": (cr if bf16 else ex) / n,
+            "flops_per_launch": ex / n,
             "algorithmic_bytes_per_launch": alg_launch,
             "credited_tflops": round(cr / (ms * 1e-3) / 1e12, 3),
             "credited_flops_per_launch": cr / n,
