@@ -139,6 +139,17 @@ inline int64_t small_rows_block(int64_t K, int64_t csize) {
 // +2-7 % at K = 128, a loss of 3-10 % at K = 64), or even K of at most 32,
 // where a kernel that keeps A in registers and walks the columns (the
 // output-bound short-K steps) takes them
+// Split K (launch::gemm, three-multiplication form): a small output over a
+// very long K, with the destination's unit slot large enough to hold the S
+// partial products past the M N outputs
+inline int64_t splitk_parts(int64_t K) {
+    const int64_t S = std::min<int64_t>(512, (K + 255) / 256);
+    const int64_t kc = ((K + S - 1) / S + 31) / 32 * 32;
+    return (K + kc - 1) / kc;
+}
+inline bool gemm_3m_splitk(int64_t M, int64_t K, int64_t N, int64_t units, int64_t sC) {
+    return M <= 64 && N <= 64 && K >= 4096 && units <= 64 && sC >= (splitk_parts(K) + 1) * M * N;
+}
 inline bool gemm_3m_fits(int64_t M, int64_t K, int64_t N) {
     return K % 2 == 0 && (K >= 128 || K <= 32) && N >= 64 && M >= 64;
 }

@@ -947,6 +947,81 @@ __global__ __launch_bounds__(256, SCAT || G > 2 ? 3 : 4) void k_gemm_3m_short(co
     }
 }
 
+// Split K for steps with a small output and a very long K (M, N <= 64,
+// K >= 4096: near the end of a path, where one output tile would run as one
+// block per unit).  Block (s, u) forms the complex64 partial product of unit
+// u over k in [s kc, (s + 1) kc) -- complex multiply-adds in FP32, A and B
+// staged through LDS 32 k at a time, each thread 16 outputs -- and writes it
+// to P[u][s][M][N]; k_splitk_sum then adds the S partials of each output in
+// order s = 0..S-1 (deterministic) and stores the sum, through the
+// fused-store tables when given.
+constexpr int SK_KT = 32;
+__global__ __launch_bounds__(256) void k_splitk_part(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                     float2 *__restrict__ P, int M, int K, int N, int kc,
+                                                     int64_t sA, int64_t sB, int64_t sP) {
+    __shared__ float2 As[64][SK_KT + 1], Bs[64][SK_KT + 1];
+    const int s = blockIdx.x;
+    const int64_t u = blockIdx.y;
+    A += u * sA;
+    B += u * sB;
+    P += u * sP + (int64_t)s * M * N;
+    const int tid = threadIdx.x;
+    const int m = tid >> 2, n0 = (tid & 3) * 16;   // rows 0..63, 16 columns each
+    float re[16], im[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) re[j] = im[j] = 0.f;
+    const int kb = s * kc, ke = min(K, kb + kc);
+    for (int k0 = kb; k0 < ke; k0 += SK_KT) {
+        // 64 rows x 32 k of A and of B: 2048 complex each, 8 per thread
+        for (int i = tid; i < 64 * SK_KT; i += 256) {
+            const int r = i / SK_KT, kk = i % SK_KT, k = k0 + kk;
+            const bool in = k < ke;
+            As[r][kk] = (r < M && in) ? A[(int64_t)r * K + k] : float2{0.f, 0.f};
+            Bs[r][kk] = (r < N && in) ? B[(int64_t)r * K + k] : float2{0.f, 0.f};
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < SK_KT; ++kk) {
+            const float2 a = As[m][kk];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const float2 b = Bs[n0 + j][kk];
+                re[j] += a.x * b.x - a.y * b.y;
+                im[j] += a.x * b.y + a.y * b.x;
+            }
+        }
+        __syncthreads();
+    }
+    if (m < M) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (n0 + j < N) P[m * N + n0 + j] = float2{re[j], im[j]};
+    }
+}
+
+template <bool SCAT>
+__global__ void k_splitk_sum(const float2 *__restrict__ P, float2 *__restrict__ C, int M, int N, int S,
+                             int64_t sP, int64_t sC, ScatterStore sc) {
+    const int64_t u = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    const float2 *p = P + u * sP + i;
+    float re = 0.f, im = 0.f;
+    for (int s = 0; s < S; ++s) {
+        const float2 v = p[(int64_t)s * M * N];
+        re += v.x;
+        im += v.y;
+    }
+    const int m = i / N, n = i - m * N;
+    float2 *c = C + u * sC;
+    if constexpr (SCAT) {
+        const int64_t mask = ((int64_t)1 << sc.shift) - 1;
+        c[sc.fa[m >> sc.shift] + sc.fb[m & mask] + sc.fg[n]] = float2{re, im};
+    } else {
+        c[(int64_t)m * N + n] = float2{re, im};
+    }
+}
+
 // FP64 MFMA GEMM with v_mfma_f64_16x16x4f64: four waves in 2 x 2, each
 // owning BI x BJ blocks of 16 x 16, so the tile is (32*BI) x (32*BJ), k-step
 // 16.  The four k-slots (lanes 16*slot .. 16*slot+15) map to k = 4*slot + t
@@ -1660,6 +1735,27 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     if (mode == 4) {
         if (K % 2 != 0) fail(TNS_E_UNSUPPORTED, "three-multiplication GEMM needs an even K");
         if (units <= 0 || M <= 0 || N <= 0) return;
+        if (gemm_3m_splitk(M, K, N, units, sC)) {
+            // split K: the partials go to the unit's own output slot past its
+            // M N outputs (the slot holds the path's largest intermediate)
+            const int64_t Sn = splitk_parts(K);
+            const int64_t kc = (K + Sn - 1) / Sn;
+            const float2 *a = (const float2 *)A, *b = (const float2 *)Bt;
+            float2 *c = (float2 *)C;
+            hipLaunchKernelGGL(k_splitk_part, dim3((unsigned)Sn, (unsigned)units), dim3(256), 0, st, a, b,
+                               c + M * N, (int)M, (int)K, (int)N, (int)kc, sA, sB, sC);
+            check_launch("splitk_part");
+            const dim3 g2((unsigned)((M * N + 255) / 256), (unsigned)units);
+            const ScatterStore none{};
+            if (sc)
+                hipLaunchKernelGGL((k_splitk_sum<true>), g2, dim3(256), 0, st, c + M * N, c, (int)M, (int)N,
+                                   (int)Sn, sC, sC, *sc);
+            else
+                hipLaunchKernelGGL((k_splitk_sum<false>), g2, dim3(256), 0, st, c + M * N, c, (int)M, (int)N,
+                                   (int)Sn, sC, sC, none);
+            check_launch("splitk_sum");
+            return;
+        }
         if (K <= 32) {
             // short K: the output dominates (K = 16: 2 groups of 8, K = 32: 4)
             if (K <= 16) launch_3m_short<2>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);

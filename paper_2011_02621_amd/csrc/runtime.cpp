@@ -489,8 +489,9 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 // (the short-K steps of the same form count with the other GEMMs)
                 const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
                                     : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
-                ev_begin(s.kernel == 3 && s.K > 32 ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
-                         (s.kernel == 3 ? 6.0 : 8.0 * prod) * mkn);
+                const bool k3m = s.kernel == 3 && s.K > 32 && !gemm_3m_splitk(s.M, s.K, s.N, g, dst.us);
+                ev_begin(k3m ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
+                         (s.kernel == 3 && !gemm_3m_splitk(s.M, s.K, s.N, g, dst.us) ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
                     launch::gemm(src.p, Bb, dst.p, g, s.M, s.K, s.N, src.us, s.K * s.N, dst.us, p.precision,
                                  stream, s.store_fused ? &p.scatter[m] : nullptr);
