@@ -714,8 +714,8 @@ def main():
                     help="MiB of a plain device copy run first (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slice "
-              "sharding is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU slice "
+              "sharding is not implemented", file=sys.stderr)
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x]
     for x in legs:
