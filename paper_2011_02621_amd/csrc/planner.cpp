@@ -1015,8 +1015,13 @@ static void compile_steps(Plan &p) {
         } else if (final_op && s.M * s.N != ((int64_t)1 << c.n_open)) {
             fail(TNS_E_BAD_PATH, "internal: final tensor does not hold the open legs");
         } else if (s.K >= 16 && s.N >= 16 && s.M >= 16 && s.K % 2 == 0) {
-            // complex64 wide steps: three real products instead of four
-            s.kernel = (p.precision == TNS_C64 && gemm_3m_fits(s.M, s.K, s.N)) ? 3 : 0;
+            // complex64 wide steps: three real products instead of four.  The
+            // split-BF16 forms keep the real embedding, except on the
+            // small-output long-K steps, which run split over K in FP32: their
+            // single long accumulation would otherwise set the amplitude's error
+            const bool splitk_shape = s.M <= 64 && s.N <= 64 && s.K >= 4096;
+            if (p.precision == TNS_C64) s.kernel = gemm_3m_fits(s.M, s.K, s.N) ? 3 : 0;
+            else s.kernel = (p.precision != TNS_C128 && splitk_shape) ? 3 : 0;
         } else {
             s.kernel = 1;
         }
