@@ -82,6 +82,31 @@ def test_many_short_requests_freed_at_once(g12):
         ctx.close()
 
 
+def test_sliced_requests_share_the_prefix(g12):
+    # cut bonds among the last sites of the path: each work item covering
+    # several slices computes the prefix once per bitstring; the served result
+    # matches the synchronous call and the oracle
+    c, bits, ref = g12
+    ctx = T.Context(0)
+    try:
+        order = [int(x) for x in ctx.plan(c, split_cycle=4, precision="c64").info().path]
+        edges = [tuple(map(int, e)) for e in c.edges]
+        cuts = [e for e, (a, b) in enumerate(edges) if min(order.index(a), order.index(b)) >= c.n - 4][:2]
+        p = ctx.plan(c, split_cycle=4, precision="c64", cuts=cuts, path=order, branches=False)
+        i = p.info()
+        assert i.n_prefix_steps > 0 and i.n_slices > 1
+        say("serving: prefix of", i.n_prefix_steps, "steps,", i.n_slices, "slices")
+        served = [ctx.submit(p, bits) for _ in range(3)]
+        outs = [r.wait().copy() for r in served]
+        sync = ctx.amplitudes(p, bits)
+        for o in outs:
+            assert np.abs(o - sync).max() <= 1e-6 * np.abs(ref).max()
+        m = compare(ref, outs[0], c.n)
+        assert m["rel_l2"] <= 1e-4 and m["max_scaled"] <= 1e-3, m
+    finally:
+        ctx.close()
+
+
 def test_two_requests_run_together():
     # two requests submitted together run concurrently: each one's run
     # interval (admission to completion) overlaps the other's
