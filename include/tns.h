@@ -147,7 +147,7 @@ typedef struct {
     const int32_t *step_kernel;     /* [n_steps] 0 MFMA GEMM (real embedding), 1 small,
                                        2 final dot, 3 MFMA GEMM in the three-multiplication
                                        form (complex64 steps with even K >= 128 or even
-                                       K <= 32, N >= 64, M >= 64) */
+                                       K <= 64, N >= 64, M >= 64) */
     const int32_t *step_permute;    /* [n_steps] 0 no permute, 1 permute launch, 2 permute done
                                        by the previous step's store (fused; a GEMM, or a
                                        small-bond step with at least 64 rows) */

@@ -136,9 +136,9 @@ inline int64_t small_rows_block(int64_t K, int64_t csize) {
 // complex64 MFMA steps that take the three-multiplication GEMM (kernel
 // class 3) and at least 64 complex columns: even K of at least 128 (its
 // block is 128 x 64; measured with fused stores: +12 % from K = 256 up,
-// +2-7 % at K = 128, a loss of 3-10 % at K = 64), or even K of at most 32,
+// +2-7 % at K = 128, a loss of 3-10 % at K = 64), or even K of at most 64,
 // where a kernel that keeps A in registers and walks the columns (the
-// output-bound short-K steps) takes them
+// output-bound short-K steps) takes them (gemm_3m_short_k)
 // Split K (launch::gemm, three-multiplication form): a small output over a
 // very long K, with the destination's unit slot large enough to hold the S
 // partial products past the M N outputs
@@ -150,8 +150,9 @@ inline int64_t splitk_parts(int64_t K) {
 inline bool gemm_3m_splitk(int64_t M, int64_t K, int64_t N, int64_t units, int64_t sC) {
     return M <= 64 && N <= 64 && K >= 4096 && units <= 64 && sC >= (splitk_parts(K) + 1) * M * N;
 }
+inline bool gemm_3m_short_k(int64_t K) { return K <= 64; }
 inline bool gemm_3m_fits(int64_t M, int64_t K, int64_t N) {
-    return K % 2 == 0 && (K >= 128 || K <= 32) && N >= 64 && M >= 64;
+    return K % 2 == 0 && (K >= 128 || K <= 64) && N >= 64 && M >= 64;
 }
 inline bool small_rows_fits(int64_t M, int64_t K, int64_t N, int64_t csize) {
     return M >= 64 && small_rows_block(K, csize) >= 8 && N * (K + 1) * csize <= kSmallRowsB;

@@ -800,9 +800,10 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
     }
 }
 
-// The three-multiplication form for short K (even K <= 32 complex): steps
-// whose output is many times their operands (K = 16 or 32 against N of
-// hundreds to thousands), so that the time goes to writing the output.  A
+// The three-multiplication form for short K (even K <= 64 complex): steps
+// whose output is many times their operands (K = 16 to 64 against N of
+// hundreds to thousands), so that the time goes to writing the output, or
+// too short for the k-loop of k_gemm_3m to hide its prologue and store.  A
 // block owns 128 rows (32 per wave) and a chunk of S3_NT column tiles of 32
 // complex; each wave keeps the re, im and (re + im) fragments of its rows,
 // all of K, in registers for the whole chunk, and the block walks the column
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
 // compute).  G k-groups of 8 complex cover K (a tail group is zero-filled).
 constexpr int S3_NT = 8;
 template <bool SCAT, int G>
-__global__ __launch_bounds__(256, SCAT || G > 2 ? 3 : 4) void k_gemm_3m_short(const float *__restrict__ A,
+__global__ __launch_bounds__(256, G > 4 ? 2 : (SCAT || G > 2 ? 3 : 4)) void k_gemm_3m_short(const float *__restrict__ A,
                                                                        const float *__restrict__ B,
                                                                        float *__restrict__ C, int64_t M, int K, int N,
                                                                        int64_t sA, int64_t sB, int64_t sC, int chunks_n,
@@ -1729,7 +1730,7 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
     // mode: 0 complex128 (FP64 MFMA), 1 complex64 (FP32 MFMA), 2 / 3 complex64 on
     // split-BF16 MFMA with 3 / 6 products, 4 complex64 in the three-
     // multiplication form (FP32 MFMA; Bt is then the plain complex [N][K], not
-    // its real embedding; K <= 32 takes the short-K kernel).  Strides arrive
+    // its real embedding; K <= 64 takes the short-K kernel).  Strides arrive
     // in complex elements; the kernels index reals.
     const hipStream_t st = (hipStream_t)stream;
     if (mode == 4) {
@@ -1756,10 +1757,11 @@ void gemm(const void *A, const void *Bt, void *C, int64_t units, int64_t M, int6
             check_launch("splitk_sum");
             return;
         }
-        if (K <= 32) {
-            // short K: the output dominates (K = 16: 2 groups of 8, K = 32: 4)
+        if (gemm_3m_short_k(K)) {
+            // short K: A stays in registers (K = 16: 2 groups of 8, 32: 4, 64: 8)
             if (K <= 16) launch_3m_short<2>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
-            else launch_3m_short<4>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
+            else if (K <= 32) launch_3m_short<4>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
+            else launch_3m_short<8>((const float *)A, (const float *)Bt, (float *)C, units, M, K, N, sA, sB, sC, st, sc);
             return;
         }
         // BJ = 2 (128 x 128 complex, one wave per SIMD) measured level with or

@@ -486,10 +486,10 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
                 // real flops the MFMA instructions execute: 8 M K N for the real
                 // embedding, 6 M K N for the three-multiplication form, times the
                 // number of products of a split-BF16 form; class 3 is k_gemm_3m
-                // (the short-K steps of the same form count with the other GEMMs)
+                // (the short-K and split-K steps count with the other GEMMs)
                 const double prod = p.precision == TNS_C64_SPLIT_BF16_3 ? 3.0
                                     : p.precision == TNS_C64_SPLIT_BF16_6 ? 6.0 : 1.0;
-                const bool k3m = s.kernel == 3 && s.K > 32 && !gemm_3m_splitk(s.M, s.K, s.N, g, dst.us);
+                const bool k3m = s.kernel == 3 && !gemm_3m_short_k(s.K) && !gemm_3m_splitk(s.M, s.K, s.N, g, dst.us);
                 ev_begin(k3m ? 3 : is_gemm ? 0 : 2, 8.0 * mkn, bytes,
                          (s.kernel == 3 && !gemm_3m_splitk(s.M, s.K, s.N, g, dst.us) ? 6.0 : 8.0 * prod) * mkn);
                 if (s.kernel == 0)
