@@ -81,8 +81,8 @@ struct Request {
     double item_flops = 0;               // planned contraction flops of one item
     std::vector<double> part;            // [n][n_schunks][opu][2] when n_schunks > 1
     int running = 0;                     // items in flight
-    volatile int cancel = 0;
-    tns_status status = TNS_OK;
+    std::atomic<int> cancel{0};          // set by tns_cancel, read by the worker mid-item
+    tns_status status = TNS_OK;          // written with both the server's lock and m held
     bool done = false;
     std::string error;
     clk::time_point t_submit, t_start, t_end;
@@ -95,6 +95,7 @@ struct Item {
     Request *r = nullptr;
     int64_t b0 = 0, b1 = 0, s0 = 0, s1 = 0, si = 0;
     bool release_first = false;
+    uint64_t release_bytes = 0;   // reservation of the cache freed before the item runs
     uint64_t budget = 0;
 };
 
@@ -140,24 +141,29 @@ struct Server {
         for (auto &t : workers) t.join();
         // requests left without workers end as cancelled (their plans are
         // destroyed first, so normally none is left)
-        for (Request *r : active) {
-            r->plan->serving_in_flight--;
-            std::lock_guard<std::mutex> lk(r->m);
-            if (r->status == TNS_OK) {
-                r->status = TNS_E_CANCELLED;
-                r->error = "context finalized";
+        {
+            std::lock_guard<std::mutex> lk_server(m);
+            for (Request *r : active) {
+                r->plan->serving_in_flight--;
+                std::lock_guard<std::mutex> lk(r->m);
+                if (r->status == TNS_OK) {
+                    r->status = TNS_E_CANCELLED;
+                    r->error = "context finalized";
+                }
+                r->t_end = clk::now();
+                r->done = true;
+                r->cv.notify_all();
             }
-            r->t_end = clk::now();
-            r->done = true;
-            r->cv.notify_all();
+            active.clear();
         }
-        active.clear();
         for (size_t i = 0; i < streams.size(); ++i) {
             ws[i].release(ctx, streams[i]);
             (void)hipStreamDestroy((hipStream_t)streams[i]);
         }
     }
 
+    // called with m held (lock order: the server's m, then r->m), so that
+    // pick() and complete_if_done() may read r->status under m alone
     void finish(Request *r, tns_status st, const std::string &err) {
         std::lock_guard<std::mutex> lk(r->m);
         if (st != TNS_OK && r->status == TNS_OK) {
@@ -179,9 +185,10 @@ struct Server {
         double best_left = 0;
         for (Request *r : active) {
             if (r->next_item >= r->n_items || r->status != TNS_OK || r->cancel) continue;
+            // a worker that switches plans frees its cache only after the
+            // pick, so until then the old reservation counts beside the new
             const bool reuse = held_plan[w] == r->plan && held[w] >= r->item_bytes;
-            const uint64_t mine = reuse ? held[w] : r->item_bytes;
-            if (reserved - held[w] + mine > pool) {
+            if (!reuse && reserved + r->item_bytes > pool) {
                 blocked = true;
                 continue;
             }
@@ -198,7 +205,8 @@ struct Server {
             it = Item{};
             it.r = r;
             it.release_first = !reuse && held[w] > 0;
-            reserved = reserved - held[w] + mine;
+            it.release_bytes = reuse ? 0 : held[w];
+            if (!reuse) reserved += mine;
             held[w] = mine;
             held_plan[w] = r->plan;
             it.budget = mine;
@@ -297,7 +305,14 @@ struct Server {
             std::string err;
             RunStats rs;
             try {
-                if (it.release_first) ws[wi].release(ctx, streams[wi]);
+                if (it.release_first) {
+                    ws[wi].release(ctx, streams[wi]);
+                    {
+                        std::lock_guard<std::mutex> lk(m);
+                        reserved -= it.release_bytes;
+                    }
+                    cv.notify_all();
+                }
                 const Plan &p = *r->plan;
                 const int64_t nb = it.b1 - it.b0, opu = p.out_per_unit;
                 double *out = r->amps + 2 * it.b0 * opu;
@@ -318,9 +333,9 @@ struct Server {
                 st = TNS_E_DEVICE;
                 err = e.what();
             }
-            if (st != TNS_OK) finish(r, st, err);
             {
                 std::lock_guard<std::mutex> lk(m);
+                if (st != TNS_OK) finish(r, st, err);
                 // the workspace may have grown within this worker's reservation
                 r->running--;
                 if (st == TNS_OK) r->finished_items++;

@@ -392,7 +392,7 @@ struct FrugalAccept {
 // are then unused.
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
-                    const volatile int *cancel, uint64_t budget, int64_t slice_begin = 0,
+                    const std::atomic<int> *cancel, uint64_t budget, int64_t slice_begin = 0,
                     int64_t slice_end = -1, const FrugalAccept *frugal = nullptr,
                     const uint8_t *bits_dev = nullptr, double *amps_dev = nullptr);
 int64_t max_bitstrings_per_batch(const Ctx *ctx, const Plan &p, uint64_t budget, int64_t n_sl);

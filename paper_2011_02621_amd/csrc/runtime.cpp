@@ -318,7 +318,7 @@ struct Timer {
 
 void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host,
                     double *amps_host, void *stream, Workspace &ws, RunStats &st,
-                    const volatile int *cancel, uint64_t budget, int64_t slice_begin,
+                    const std::atomic<int> *cancel, uint64_t budget, int64_t slice_begin,
                     int64_t slice_end, const FrugalAccept *frugal, const uint8_t *bits_dev_in,
                     double *amps_dev_out) {
     const Circuit &c = p.circ;
@@ -341,7 +341,7 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         site_total += p.site_elems[q];
     }
     for (int64_t b0 = 0; b0 < n; b0 += nb_max) {
-        if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+        if (cancel && cancel->load(std::memory_order_relaxed)) fail(TNS_E_CANCELLED, "request cancelled");
         const int64_t nb = std::min(nb_max, n - b0);
         const int64_t units = nb * n_sl;
         // every workspace slot of the batch is taken before its first launch
@@ -517,13 +517,13 @@ void run_amplitudes(Ctx *ctx, const Plan &p, int64_t n, const uint8_t *bits_host
         // the slice prefix, once per bitstring of the batch (G at a time)
         const size_t P = share ? (size_t)p.prefix_steps : 0;
         for (int64_t pb0 = 0; share && pb0 < nb; pb0 += G) {
-            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+            if (cancel && cancel->load(std::memory_order_relaxed)) fail(TNS_E_CANCELLED, "request cancelled");
             const int64_t g = std::min(G, nb - pb0);
             const Buf out{pre + (size_t)pb0 * p.prefix_elems * elem, p.prefix_elems};
             run_steps(0, P, g, pb0, 1, 0, Buf{nullptr, 0}, &out);
         }
         for (int64_t ug0 = 0; ug0 < units; ug0 += G) {
-            if (cancel && *cancel) fail(TNS_E_CANCELLED, "request cancelled");
+            if (cancel && cancel->load(std::memory_order_relaxed)) fail(TNS_E_CANCELLED, "request cancelled");
             const int64_t g = std::min(G, units - ug0);
             Buf start{nullptr, 0};
             if (share) {
