@@ -610,18 +610,20 @@ __global__ __launch_bounds__(256) void k_gemm_c64(const float *__restrict__ A,
 // three real products of M x K x N instead of the four that the real
 // embedding of the other kernels multiplies (6 M K N flops instead of 8).
 // Loads read interleaved complex pairs; the LDS store writes two planes (re,
-// im) of A and of B, and the (re + im) fragments are formed in registers
-// after each fragment read (a third of the LDS traffic and 36 KB of LDS per
-// block instead of 55 KB; +1.7 % on the 53-qubit depth-12 slices, results
-// unchanged: the same FP32 sum, formed later).  Four waves in 2 x 2, each owning 64 rows x
-// 32 BJ complex columns (2 BJ blocks of 32 x 32 per product), so the block is
-// 128 x 64 BJ complex; k-step 8 complex; two LDS stages with the next tile in
-// registers and the tile after it fetched right behind, one barrier per tile
-// placed half-way through its MFMAs, and double-buffered fragments (see the
-// loop).  K is even (pairs never straddle the end of K).
+// im) of A and of B, and the (re + im) operands are formed in registers
+// right before the MFMAs that take them (a third of the LDS traffic and 36 KB
+// of LDS per block instead of 55 KB; +1.7 % on the 53-qubit depth-12 slices,
+// results unchanged: the same FP32 sum, formed later).  Four waves in 2 x 2,
+// each owning 64 rows x 32 BJ complex columns (2 BJ blocks of 32 x 32 per
+// product), so the block is 128 x 64 BJ complex; k-step 8 complex; two LDS
+// stages with the next tile in registers and the tile after it fetched right
+// behind, one barrier per tile, and one set of fragments in registers, which
+// keeps a wave under 168 VGPRs: three waves per SIMD (three blocks per CU)
+// hide each other's barrier and LDS waits.  K is even (pairs never straddle
+// the end of K).
 constexpr int M3_BKC = 8, M3_LD = M3_BKC + 4;   // complex k per tile, floats per plane row
 template <bool SCAT, bool FULLK, int BJ>
-__global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *__restrict__ A, const float *__restrict__ B,
+__global__ __launch_bounds__(256, BJ == 1 ? 3 : 1) void k_gemm_3m(const float *__restrict__ A, const float *__restrict__ B,
                                                  float *__restrict__ C, int64_t M, int K, int N,
                                                  int64_t sA, int64_t sB, int64_t sC, int tiles_n,
                                                  ScatterStore sc, int64_t row0) {
@@ -691,69 +693,59 @@ __global__ __launch_bounds__(256, BJ == 1 ? 2 : 1) void k_gemm_3m(const float *_
     // the four MFMAs q of the tile, one 16-byte LDS read per plane and block
     const int arow = (wm * BI * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
     const int brow = (wn * BJ * 32 + (lane & 31)) * LD + 4 * (lane >> 5);
-    v4f fa[2][3][BI], fb[2][3][BJ];
-    auto frags = [&](int buf, int st) {
+    v4f fa[2][BI], fb[2][BJ];   // re and im planes of the tile's fragments
+    auto frags = [&](int st) {
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
 #pragma unroll
-            for (int i = 0; i < BI; ++i) fa[buf][p][i] = *reinterpret_cast<const v4f *>(As(st, p) + arow + i * 32 * LD);
+            for (int i = 0; i < BI; ++i) fa[p][i] = *reinterpret_cast<const v4f *>(As(st, p) + arow + i * 32 * LD);
 #pragma unroll
-            for (int j = 0; j < BJ; ++j) fb[buf][p][j] = *reinterpret_cast<const v4f *>(Bs(st, p) + brow + j * 32 * LD);
+            for (int j = 0; j < BJ; ++j) fb[p][j] = *reinterpret_cast<const v4f *>(Bs(st, p) + brow + j * 32 * LD);
         }
-#pragma unroll
-        for (int i = 0; i < BI; ++i) fa[buf][2][i] = fa[buf][0][i] + fa[buf][1][i];
-#pragma unroll
-        for (int j = 0; j < BJ; ++j) fb[buf][2][j] = fb[buf][0][j] + fb[buf][1][j];
     };
-    auto mfmas = [&](int buf, int q) {
+    auto mfmas = [&](int q) {
+        float sa[BI], sb[BJ];
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int i = 0; i < BI; ++i) sa[i] = fa[0][i][q] + fa[1][i][q];
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) sb[j] = fb[0][j][q] + fb[1][j][q];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int i = 0; i < BI; ++i)
 #pragma unroll
                 for (int j = 0; j < BJ; ++j)
-                    acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[buf][p][i][q], fb[buf][p][j][q], acc[p][i][j], 0, 0, 0);
+                    acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[p][i][q], fb[p][j][q], acc[p][i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+            for (int j = 0; j < BJ; ++j)
+                acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[i], sb[j], acc[2][i][j], 0, 0, 0);
     };
     const int nt = (K + M3_BKC - 1) / M3_BKC;
     fetch(0);
     stash(0);
     if (nt > 1) fetch(M3_BKC);
     __syncthreads();
-    frags(0, 0);
-    // Tile t (fragments in registers, buffer t % 2): half of its MFMAs, then
-    // tile t+1 from registers into the other stage (last read for tile t-1,
-    // before the previous barrier), the fetch of tile t+2, the barrier, and
-    // tile t+1's fragments read from LDS while the second half of tile t's
-    // MFMAs runs, so no LDS latency sits between a barrier and the next MFMA.
-    // The body has no branch (the last tile is peeled off and the fetch past
-    // it reads the last tile again), so the compiler schedules the stores and
-    // loads among the MFMAs of the whole stretch between two barriers.
-    auto body = [&](int t, int buf) {
+    frags(0);
+    // Tile t (fragments in registers): its MFMAs with tile t+1 written from
+    // registers into the other stage (last read for tile t-1, before the
+    // previous barrier) and tile t+2 fetched among them, then the barrier and
+    // tile t+1's fragments.  The fetch past the last tile reads the last tile
+    // again, so the body has no branch.
+    for (int t = 0; t + 1 < nt; ++t) {
         const int st = t & 1;
-        mfmas(buf, 0);
-        mfmas(buf, 1);
+        mfmas(0);
+        mfmas(1);
         stash(st ^ 1);
         fetch(std::min(t + 2, nt - 1) * M3_BKC);
+        mfmas(2);
+        mfmas(3);
         __syncthreads();
-        frags(buf ^ 1, st ^ 1);
-        mfmas(buf, 2);
-        mfmas(buf, 3);
-    };
-    auto last = [&](int buf) {
+        frags(st ^ 1);
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) mfmas(buf, q);
-    };
-    int t = 0;
-    for (; t + 2 < nt; t += 2) {   // two tiles per trip: static fragment buffers
-        body(t, 0);
-        body(t + 1, 1);
-    }
-    if (t + 1 < nt) {
-        body(t, 0);
-        last(1);
-    } else {
-        last(0);
-    }
+    for (int q = 0; q < 4; ++q) mfmas(q);
     __syncthreads();   // the stages are reused for the store
     // 32x32 accumulator layout: lane holds complex column lane%32 of its block
     // and rows 8*(r/4) + 4*(lane/32) + r%4 for its 16 values r
