@@ -63,6 +63,38 @@ def test_sample_frugal_argument_errors(ctx):
     assert e.value.name == "TNS_E_NO_DEVICE"
 
 
+def test_serving_argument_errors():
+    # host-side checks of the serving calls: knob ranges, a planning-only
+    # context, and NULL request handles
+    import ctypes
+    lib = T.load_library()
+    c = T.Context(-1)
+    try:
+        for kw in ({"n_workers": 17}, {"n_workers": -1}, {"item_flops": -1.0},
+                   {"item_flops": float("nan")}):
+            with pytest.raises(T.TnsError) as e:
+                c.configure_serving(**kw)
+            assert e.value.name == "TNS_E_INVALID_ARG", kw
+        c.configure_serving(n_workers=2, item_flops=1e12)   # accepted before any submit
+        circ, bits = config("grid3x4_d8")
+        p = c.plan(circ, precision="c64")
+        with pytest.raises(T.TnsError) as e:
+            c.submit(p, bits[:2])
+        assert e.value.name == "TNS_E_NO_DEVICE"
+        p.close()
+    finally:
+        c.close()
+    d = ctypes.c_int(7)
+    t, r = ctypes.c_double(), ctypes.c_double()
+    assert T.STATUS[lib.tns_poll(None, ctypes.byref(d))] == "TNS_E_INVALID_ARG"
+    assert T.STATUS[lib.tns_wait(None)] == "TNS_E_INVALID_ARG"
+    assert T.STATUS[lib.tns_cancel(None)] == "TNS_E_INVALID_ARG"
+    assert T.STATUS[lib.tns_request_latency(None, ctypes.byref(t), ctypes.byref(r))] == "TNS_E_INVALID_ARG"
+    assert lib.tns_request_free(None) == 0
+    assert lib.tns_plan_destroy(None) == 0
+    assert lib.tns_finalize(None) == 0
+
+
 def test_bad_circuits(ctx):
     good = _two_qubit_circuit(2, [(0, 1)], [(0, 1, 0, fsim(np.pi / 2, np.pi / 6))])
     ctx.plan(good)
