@@ -93,3 +93,26 @@ def test_first_chi4_gate_leaves_the_printed_bond(ctx):
     for g in (ISWAP, fsim(np.pi / 2, np.pi / 6)):
         c = Circuit(2, [(0, 1)], [Gate(0, 1, 0, g)], 1)
         assert list(ctx.plan(c, split_cycle=1).info().bond_ket) == [int(PV["first_bond_chi4"])]
+
+
+def _operator_schmidt(g):
+    # O[(a b), (a' b')] regrouped as M[(a a'), (b b')]; its singular values
+    # are the operator Schmidt coefficients of the split O = sum_s P_s (x) Q_s
+    o = np.asarray(g, complex).reshape(2, 2, 2, 2)      # a, b, a', b'
+    m = o.transpose(0, 2, 1, 3).reshape(4, 4)
+    return np.linalg.svd(m, compute_uv=False)
+
+
+@pytest.mark.parametrize("gate,key,sigma", [
+    (CZ, "chi_controlled", [np.sqrt(2), np.sqrt(2), 0, 0]),
+    (CNOT, "chi_controlled", [np.sqrt(2), np.sqrt(2), 0, 0]),
+    (ISWAP, "chi_iswap", [1, 1, 1, 1]),
+    (fsim(np.pi / 2, np.pi / 6), "chi_fsim", [1, 1, 1, 1]),
+])
+def test_generator_gates_have_the_printed_split_rank(gate, key, sigma):
+    # the circuit generator's matrices split with the rank the paper prints;
+    # the coefficients' squares add up to the Frobenius norm squared, 4
+    s = _operator_schmidt(gate)
+    assert int((s > 1e-12).sum()) == int(PV[key])
+    assert np.allclose(s, sigma, atol=1e-12)
+    assert np.isclose((s ** 2).sum(), 4.0, atol=1e-12)
